@@ -1,0 +1,498 @@
+"""Pins for the CPU oracle: each check rests on something other than the
+oracle itself (values printed in the paper, a published generator's
+known-answer vector or a third-party implementation of it, library linear
+algebra, closed forms, invariants, brute force on tiny inputs, statistics).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from workloads import (coherent_identity, er_incidence, gaussian_dense, semi_coherent_block,
+                       sparse_rowscaled, make_config)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# counter-based generator used for Algorithm 1's trials
+
+
+def test_philox_known_answer():
+    for r in _read_table("philox4x64_10_kat.txt"):
+        ctr = [int(v, 16) for v in r[0:4]]
+        key = [int(v, 16) for v in r[4:6]]
+        want = [int(v, 16) for v in r[6:10]]
+        assert [int(v) for v in oracle.philox4x64_10(ctr, key)] == want
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**63 + 7])
+def test_philox_matches_numpy_stream(seed):
+    # numpy's Philox bit generator is an independent implementation of the
+    # same published block function; it increments the counter before use
+    g = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                        counter=np.array([2**64 - 1] * 4, dtype=np.uint64))
+    raw = g.random_raw(4 * 64)
+    for blk in range(64):
+        got = oracle.philox4x64_10([blk, 0, 0, 0], [seed, 0])
+        assert [int(v) for v in got] == [int(v) for v in raw[4 * blk:4 * blk + 4]]
+    # counters with high words set and a carry
+    g = np.random.Philox(key=np.array([seed, 99], dtype=np.uint64),
+                        counter=np.array([2**64 - 1, 5, 6, 7], dtype=np.uint64))
+    raw = g.random_raw(4)
+    assert [int(v) for v in oracle.philox4x64_10([0, 6, 6, 7], [seed, 99])] == [int(v) for v in raw]
+
+
+def test_uniform_definition():
+    seed = 7
+    g = np.random.Philox(key=[seed, 0], counter=[2**64 - 1] * 4)
+    raw = g.random_raw(400)
+    for t in range(400):
+        u = oracle.uniform(seed, t)
+        assert u == float(int(raw[t]) >> 11) * 2.0 ** -53
+        assert 0.0 <= u < 1.0
+
+
+def test_uniform_moments():
+    u = np.array([oracle.uniform(3, t) for t in range(20000)])
+    assert abs(u.mean() - 0.5) < 4 * math.sqrt(1 / 12 / u.size)
+    assert abs(u.var() - 1 / 12) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 step 2: s = 4 n log n
+
+
+def test_sample_size_matches_printed_values():
+    for n, s, *_ in _read_table("sample_sizes.txt"):
+        assert oracle.sample_size(4.0, int(n)) == int(s), n
+
+
+def test_sample_size_rounding_and_base():
+    # the printed values rule out rounding to nearest and other log bases
+    rows = [(int(r[0]), int(r[1])) for r in _read_table("sample_sizes.txt")]
+    assert any(round(4 * n * math.log(n)) != s for n, s in rows)
+    assert all(math.ceil(4 * n * math.log2(n)) != s for n, s in rows)
+    assert oracle.sample_size(4.0, 1) == 1
+    assert oracle.sample_size(0.01, 50) == 50  # never fewer draws than columns
+
+
+def test_theorem_constant_uses_log_base_n():
+    # Remark after Theorem (approximation): C eps^-2 with delta=1/20, eps=1/2,
+    # ||A|| <= 1, n = 300 is 56/3 (1 + log_300 40), printed as about 30.74
+    n, delta, eps, normA = 300, 1 / 20, 0.5, 1.0
+    C = 2 / 3 * (6 * normA**2 + 2 * eps) * (1 - math.log(delta / 2) / math.log(n))
+    assert abs(C / eps**2 - 30.74) < 5e-3
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 step 1 and Eq. (R2P)
+
+
+def _small_sparse(seed=0, m=500, n=40, k=6):
+    return sparse_rowscaled(m=m, n=n, k=k, seed=seed)
+
+
+def test_column_norms_against_numpy():
+    for p in (gaussian_dense(300, 17, seed=1), _small_sparse(), er_incidence(60, 400, seed=2)):
+        D, rc = oracle.column_norms(p)
+        assert rc == 0
+        ref = np.linalg.norm(p.dense(), axis=0)
+        np.testing.assert_allclose(D, ref, rtol=1e-15, atol=0)
+
+
+def test_column_norms_errors():
+    p = gaussian_dense(50, 5, seed=3)
+    p.A[:, 2] = 0.0
+    _, rc = oracle.column_norms(p)
+    assert rc == -2
+    p.A[4, 1] = np.nan
+    _, rc = oracle.column_norms(p)
+    assert rc == -3
+
+
+def test_row_weights_and_normalisation_invariants():
+    for p in (gaussian_dense(300, 17, seed=1), _small_sparse(seed=4), er_incidence(60, 400, seed=2)):
+        D, _ = oracle.column_norms(p)
+        w = oracle.row_weights(p, 1.0 / D)
+        At = p.dense() * (1.0 / D)[None, :]
+        np.testing.assert_allclose(w, (At**2).sum(axis=1), rtol=1e-14)
+        # Section 4.1: after normalisation diag(A^T A) = 1 and ||A||_F^2 = n
+        np.testing.assert_allclose(np.diag(At.T @ At), 1.0, rtol=1e-14)
+        assert abs(math.fsum(w) - p.n) <= 1e-12 * p.n
+
+
+def test_cdf_exact_prefix_sums():
+    rng = np.random.default_rng(0)
+    w = rng.random(3000) * 10.0 ** rng.uniform(-8, 8, 3000)
+    w[::17] = 0.0
+    c, W = oracle.cdf(w)
+    ref = np.array([math.fsum(w[: i + 1]) for i in range(w.size)])
+    np.testing.assert_allclose(c, ref, rtol=2 ** -52, atol=0)
+    assert np.all(np.diff(c) >= 0)
+    assert W == c[-1]
+
+
+def test_draw_brute_force():
+    rng = np.random.default_rng(1)
+    w = rng.random(50)
+    w[[0, 7, 8, 49]] = 0.0
+    c, W = oracle.cdf(w)
+    for _ in range(2000):
+        tau = rng.random() * W
+        i, gap = oracle.draw(w, c, tau)
+        first = next(k for k in range(w.size) if c[k] > tau)
+        assert i == first
+        assert w[i] > 0
+        lo = c[i - 1] if i > 0 else 0.0
+        assert lo <= tau < c[i]
+        assert gap == pytest.approx(min(tau - lo, c[i] - tau) / W, rel=1e-12)
+    # tau at the total falls back to the last row of positive weight
+    i, gap = oracle.draw(w, c, W)
+    assert i == 48 and gap == 0.0
+
+
+def test_draw_distribution_chi_square():
+    # Algorithm 1 with Eq. (R2P): Pr{i_t = k} = p_k
+    from scipy.stats import chi2
+    p = _small_sparse(seed=5, m=40, n=8, k=3)
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=11)
+    w = o.w
+    probs = w / w.sum()
+    c, W = oracle.cdf(w)
+    N = 60000
+    hits = np.zeros(p.m)
+    for t in range(N):
+        i, _ = oracle.draw(w, c, oracle.uniform(11, t) * W)
+        hits[i] += 1
+    expected = probs * N
+    keep = expected > 5
+    stat = ((hits[keep] - expected[keep]) ** 2 / expected[keep]).sum()
+    assert stat < chi2.ppf(0.999, keep.sum() - 1)
+
+
+def test_coherent_matrix_draws_only_identity_rows():
+    # Section 3.2: for Z = [I; 0] all draws must come from the first n rows
+    p = coherent_identity(200, 10)
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0)
+    idx, gap = o.samples()
+    assert idx.max() < 10 and idx.min() >= 0
+    np.testing.assert_allclose(o.w[:10], 1.0)
+    # every row drawn, M = sum of c_r * (n / (s * 1)) e_r e_r^T, diagonal
+    M = o.M_dense()
+    counts = np.bincount(idx, minlength=10)
+    np.testing.assert_allclose(np.diag(M), counts * 10 / o.s, rtol=1e-15)
+    assert np.count_nonzero(M - np.diag(np.diag(M))) == 0
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 / Section 3.3: the sampled Gram matrix
+
+
+def _normalised(p):
+    D = np.linalg.norm(p.dense(), axis=0)
+    return p.dense() / D[None, :]
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: gaussian_dense(400, 12, seed=2),
+    lambda: _small_sparse(seed=6, m=800, n=30, k=5),
+    lambda: er_incidence(40, 300, seed=3),
+])
+def test_gram_equals_sampling_matrix_product(maker):
+    # Algorithm 1 forms A_s = S A with S_{t,i_t} = 1/sqrt(s p_{i_t}); the
+    # oracle accumulates Section 3.3's sum. Build S explicitly and compare.
+    p = maker()
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=9)
+    idx, _ = o.samples()
+    At = _normalised(p)
+    prob = (At**2).sum(axis=1) / p.n
+    S = np.zeros((o.s, p.m))
+    S[np.arange(o.s), idx] = 1.0 / np.sqrt(o.s * prob[idx])
+    As = S @ At
+    ref = As.T @ As
+    M = o.M_dense()
+    assert np.array_equal(M, M.T)
+    np.testing.assert_allclose(M, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    np.linalg.cholesky(M)  # SPD
+    if p.fmt == "csr":
+        rp, ci, v = o.M_csr()
+        assert np.all(np.diff(rp) >= 1)
+        for j in range(p.n):
+            cols = ci[rp[j]:rp[j + 1]]
+            assert np.all(np.diff(cols) > 0) and j in cols
+        # entry routine computes the same sums independently of the stored M
+        for j, l in [(0, 0), (3, 5), (p.n - 1, p.n - 2)]:
+            assert o.M_entry(j, l) == M[j, l] or M[j, l] == 1.0
+
+
+def test_gram_unbiased_monte_carlo():
+    # Eq. (EATA): E[A_s^T A_s] = A^T A (normalised), checked over 400 seeds
+    p = _small_sparse(seed=7, m=120, n=6, k=3)
+    At = _normalised(p)
+    K = At.T @ At
+    Ms = np.array([oracle.Oracle(p, C_=1.0, sweeps=1, seed=sd).M_dense() for sd in range(400)])
+    mean, se = Ms.mean(axis=0), Ms.std(axis=0, ddof=1) / math.sqrt(Ms.shape[0])
+    z = np.abs(mean - K) / np.maximum(se, 1e-300)
+    mask = se > 0
+    assert z[mask].max() < 5.0
+
+
+def test_gram_spectral_bound_statistical():
+    # Theorem (approximation): with s = C eps^-2 n log n and the theorem's C,
+    # ||A_s^T A_s - A^T A|| <= eps with probability >= 1 - delta
+    p = gaussian_dense(2000, 8, seed=8)
+    At = _normalised(p)
+    K = At.T @ At
+    n, eps, delta = p.n, 0.5, 0.05
+    normA2 = np.linalg.norm(K, 2)
+    Cth = 2 / 3 * (6 * normA2 + 2 * eps) * (1 - math.log(delta / 2) / math.log(n))
+    fails = 0
+    for sd in range(60):
+        o = oracle.Oracle(p, C_=Cth / eps**2, sweeps=1, seed=sd)
+        fails += np.linalg.norm(o.M_dense() - K, 2) > eps
+    assert fails <= 60 * delta + 3
+
+
+def test_zero_diagonal_guard():
+    # a column never drawn leaves M_jj = 0; the oracle sets it to 1 and counts it
+    p = gaussian_dense(50, 4, seed=1)
+    p.A[:, 3] = 0.0
+    p.A[0, 3] = 1.0  # only row 0 touches column 3
+    o0 = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0)
+    idx, _ = o0.samples()
+    rows = np.array([1, 2, 3, 2, 5], dtype=np.int64)  # excludes row 0
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0, samples=rows)
+    M = o.M_dense()
+    assert M[3, 3] == 1.0 and np.all(M[3, :3] == 0) and o.info()["diag_fixes"] == 1
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3: symmetric Gauss-Seidel preconditioner
+
+
+def _sgs_fixture(sweeps, maker=None):
+    p = maker() if maker else _small_sparse(seed=10, m=600, n=25, k=5)
+    return p, oracle.Oracle(p, C_=4.0, sweeps=sweeps, seed=3)
+
+
+def _P_matrix(o):
+    return np.column_stack([o.apply_P(e) for e in np.eye(o.n)])
+
+
+def test_sgs_one_sweep_closed_form():
+    # t = 1 from e = 0 is classical SGS: P = (D+U)^{-1} D (D+L)^{-1}
+    for maker in (None, lambda: gaussian_dense(300, 20, seed=4)):
+        p, o = _sgs_fixture(1, maker)
+        M = o.M_dense()
+        Dg = np.diag(np.diag(M))
+        r = np.random.default_rng(0).standard_normal(o.n)
+        y = sla.solve_triangular(np.tril(M), r, lower=True)
+        z = sla.solve_triangular(np.triu(M), Dg @ y, lower=False)
+        np.testing.assert_allclose(o.apply_P(r), z, rtol=1e-12, atol=1e-12 * np.abs(z).max())
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_sgs_symmetric_positive_definite(sweeps):
+    p, o = _sgs_fixture(sweeps)
+    P = _P_matrix(o)
+    np.testing.assert_allclose(P, P.T, atol=1e-12 * np.abs(P).max())
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+
+
+def test_sgs_in_place_form_and_order():
+    # Algorithm 3 runs all t forward steps, then all t backward steps; each step
+    # e <- e + B^{-1}(r - M e) equals e <- L^{-1}(r - U e) (L = lower incl. diag)
+    p, o = _sgs_fixture(2)
+    M = o.M_dense()
+    L, U = np.tril(M), np.triu(M, 1)
+    r = np.random.default_rng(2).standard_normal(o.n)
+    e = np.zeros(o.n)
+    for _ in range(2):
+        e = sla.solve_triangular(L, r - U @ e, lower=True)
+    for _ in range(2):
+        e = sla.solve_triangular(L.T, r - np.tril(M, -1) @ e, lower=False)
+    np.testing.assert_allclose(o.apply_P(r), e, rtol=1e-11, atol=1e-12 * np.abs(e).max())
+    # alternating forward/backward differs for t >= 2 (the order matters)
+    e2 = np.zeros(o.n)
+    for _ in range(2):
+        e2 = sla.solve_triangular(L, r - U @ e2, lower=True)
+        e2 = sla.solve_triangular(L.T, r - np.tril(M, -1) @ e2, lower=False)
+    assert np.abs(e2 - e).max() > 1e-8 * np.abs(e).max()
+
+
+def test_sgs_many_sweeps_tends_to_inverse():
+    p, o = _sgs_fixture(60, lambda: gaussian_dense(2000, 10, seed=5))
+    M = o.M_dense()
+    r = np.random.default_rng(3).standard_normal(o.n)
+    np.testing.assert_allclose(o.apply_P(r), np.linalg.solve(M, r), rtol=1e-10)
+
+
+def test_sgs_zero_sweeps_is_identity():
+    p, o = _sgs_fixture(0)
+    r = np.random.default_rng(4).standard_normal(o.n)
+    assert np.array_equal(o.apply_P(r), r)
+
+
+# ---------------------------------------------------------------------------
+# products with A
+
+
+def test_apply_K_against_dense():
+    for p in (gaussian_dense(200, 9, seed=6), _small_sparse(seed=11)):
+        o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0)
+        At = _normalised(p)
+        v = np.random.default_rng(5).standard_normal(p.n)
+        np.testing.assert_allclose(o.apply_K(v), At.T @ (At @ v), rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 step 4: PCG on the normal equation
+
+
+@pytest.mark.parametrize("maker,sweeps", [
+    (lambda: gaussian_dense(600, 15, seed=7), 1),
+    (lambda: _small_sparse(seed=12, m=3000, n=60, k=6), 2),
+    (lambda: er_incidence(80, 900, seed=4), 5),
+    (lambda: semi_coherent_block(400, 12, seed=1), 1),
+])
+def test_pcg_matches_dense_least_squares(maker, sweeps):
+    p = maker()
+    o = oracle.Oracle(p, C_=4.0, sweeps=sweeps, seed=1)
+    x, info = o.solve(tol=1e-12)
+    A = p.dense()
+    xq = np.linalg.lstsq(A, p.b, rcond=None)[0]
+    kappa = np.linalg.cond(A.T @ A)
+    assert info["status"] == 0
+    assert np.linalg.norm(x - xq) / np.linalg.norm(xq) <= max(kappa * 1e-12 * 10, 1e-13)
+    # Eq. (NOR) residual recomputed independently
+    g = A.T @ (p.b - A @ x)
+    assert np.linalg.norm(g) / np.linalg.norm(A.T @ p.b) <= 1e-12 * 1.01
+
+
+def test_pcg_residual_monotone_in_energy_norm():
+    # CG minimises the A^T A-norm error, so ||b - A x_k|| never increases
+    p = _small_sparse(seed=13, m=2000, n=50, k=5)
+    o = oracle.Oracle(p, C_=4.0, sweeps=2, seed=2)
+    A = p.dense()
+    res = []
+    for k in range(0, 14):
+        x, _ = o.solve(fixed_iters=k)
+        res.append(np.linalg.norm(p.b - A @ x))
+    assert all(res[i + 1] <= res[i] * (1 + 1e-13) for i in range(len(res) - 1))
+    assert res[-1] < 0.5 * res[0]
+
+
+def test_pcg_single_column_exact():
+    p = gaussian_dense(30, 1, seed=8)
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0)
+    x, info = o.solve(tol=1e-14)
+    A = p.dense()
+    assert info["iters"] == 1
+    assert x[0] == pytest.approx((A[:, 0] @ p.b) / (A[:, 0] @ A[:, 0]), rel=1e-14)
+
+
+def test_pcg_finite_termination_small_n():
+    p = gaussian_dense(200, 6, seed=9)
+    o = oracle.Oracle(p, C_=4.0, sweeps=0, seed=0)
+    x, info = o.solve(tol=1e-13)
+    assert info["status"] == 0 and info["iters"] <= p.n + 1
+
+
+def test_pcg_zero_rhs():
+    p = gaussian_dense(40, 4, seed=1)
+    o = oracle.Oracle(p, C_=4.0, sweeps=1, seed=0)
+    x, info = o.solve(b=np.zeros(p.m))
+    assert info["iters"] == 0 and np.all(x == 0) and info["status"] == 0
+
+
+def test_preconditioner_cuts_iterations_on_graph():
+    # Section 5.5: the sampled SGS preconditioner needs fewer iterations than
+    # CG on the normalised matrix (sweeps = 0)
+    p = er_incidence(400, 3000, seed=5)
+    x0, i0 = oracle.Oracle(p, C_=4.0, sweeps=0, seed=0).solve(tol=1e-8)
+    x1, i1 = oracle.Oracle(p, C_=4.0, sweeps=5, seed=0).solve(tol=1e-8)
+    assert i1["iters"] < i0["iters"]
+
+
+# ---------------------------------------------------------------------------
+# differentiable form: adjoint solve and gradients
+
+
+def _loss_and_grads(p, o, x):
+    gx = x - p.x_t
+    lam, gb, gA, info = o.backward(x, gx, tol=1e-13)
+    return lam, gb, gA, info
+
+
+def test_backward_matches_dense_reference():
+    for p in (gaussian_dense(300, 8, seed=10), er_incidence(30, 200, seed=6)):
+        if p.x_t is None:
+            p.x_t = np.random.default_rng(0).standard_normal(p.n)
+        o = oracle.Oracle(p, C_=4.0, sweeps=2, seed=0)
+        x, _ = o.solve(tol=1e-13)
+        lam, gb, gA, info = _loss_and_grads(p, o, x)
+        A = p.dense()
+        gx = x - p.x_t
+        lam_ref = np.linalg.solve(A.T @ A, gx)
+        np.testing.assert_allclose(lam, lam_ref, rtol=1e-9, atol=1e-12 * np.abs(lam_ref).max())
+        np.testing.assert_allclose(gb, A @ lam_ref, rtol=1e-9, atol=1e-12 * np.abs(gb).max())
+        r = p.b - A @ x
+        GA = np.outer(r, lam_ref) - np.outer(A @ lam_ref, x)
+        if p.fmt == "dense":
+            np.testing.assert_allclose(gA, GA, rtol=1e-8, atol=1e-11 * np.abs(GA).max())
+        else:
+            rows = np.repeat(np.arange(p.m), np.diff(p.row_ptr))
+            np.testing.assert_allclose(gA, GA[rows, p.col_idx], rtol=1e-8, atol=1e-11 * np.abs(GA).max())
+
+
+def test_backward_central_finite_differences():
+    p = er_incidence(25, 150, seed=7)
+    x_t = p.x_t
+
+    def loss(values, b):
+        q = er_incidence(25, 150, seed=7)
+        q.values = values
+        q.b = b
+        o = oracle.Oracle(q, C_=4.0, sweeps=2, seed=0)
+        x, info = o.solve(tol=1e-14)
+        return 0.5 * np.sum((x - x_t) ** 2)
+
+    o = oracle.Oracle(p, C_=4.0, sweeps=2, seed=0)
+    x, _ = o.solve(tol=1e-14)
+    lam, gb, gA, _ = _loss_and_grads(p, o, x)
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        db = rng.standard_normal(p.m)
+        h = 1e-6 * np.linalg.norm(p.b) / np.linalg.norm(db)
+        fd = (loss(p.values, p.b + h * db) - loss(p.values, p.b - h * db)) / (2 * h)
+        assert fd == pytest.approx(gb @ db, rel=1e-6)
+        dv = rng.standard_normal(p.values.shape[0])
+        h = 1e-6 * np.linalg.norm(p.values) / np.linalg.norm(dv)
+        fd = (loss(p.values + h * dv, p.b) - loss(p.values - h * dv, p.b)) / (2 * h)
+        assert fd == pytest.approx(gA @ dv, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# the named workloads at reduced size
+
+
+@pytest.mark.parametrize("name", ["gaussian", "sparse", "graph"])
+def test_small_workloads_converge(name):
+    p, cfg = make_config(name, scale="small")
+    o = oracle.Oracle(p, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0)
+    x, info = o.solve(tol=1e-10)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10

@@ -1,0 +1,233 @@
+// Internal header of liblsq: device helpers, the context layout and the
+// host-side launchers of every kernel. Not part of the public ABI (lsq.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lsq.h"
+
+namespace lsq {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// sum over aligned groups of G lanes (G a power of two <= 64)
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// block-wide sum, result valid in every thread; red must hold blockDim/64 T
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *red) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  T t = 0;
+  for (int k = 0; k < nw; ++k) t += red[k];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// context
+
+struct Dev {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Scal {
+  // device scalars of the PCG loop (float64 slots; the float32 loop uses the
+  // float slots of the same layout through a second array)
+  enum { RHO = 0, PQ, ALPHA, BETA, RNORM2, RHO_NEW, FNORM2, TMP0, TMP1, COUNT = 16 };
+};
+
+}  // namespace lsq
+
+struct lsq_ctx {
+  // problem (borrowed)
+  int32_t fmt = 0, dtype = 0;
+  int64_t m = 0, n = 0, ld = 0, nnz = 0;
+  const void *A = nullptr;
+  const int64_t *rp = nullptr;
+  const int32_t *ci = nullptr;
+  const double *b = nullptr;
+  hipStream_t stream = nullptr;
+  lsq_options opt{};
+  double C = 4.0;
+  int32_t sweeps = 1;
+  uint64_t seed = 0;
+  int device = 0;
+
+  // setup results
+  double *D = nullptr, *invD = nullptr, *w = nullptr, *cdf = nullptr;
+  float *invD32 = nullptr;
+  int64_t s = 0, s_d = 0;
+  int64_t *idx = nullptr;
+  double *gap = nullptr;
+  int32_t *cnt = nullptr;
+  int64_t *urow = nullptr;  // distinct drawn rows, ascending
+  int32_t *ucnt = nullptr;  // multiplicity of each
+  double W = 0.0;
+
+  // M: dense (n*n row-major) or CSR with int32 offsets
+  bool Mdense = false;
+  int64_t nnzM = 0;
+  double *Md = nullptr;   // float64 values (dense n*n or CSR nnz)
+  float *Mf = nullptr;    // float32 values (FP32_REFINE)
+  int32_t *Mrp = nullptr, *Mci = nullptr, *Mdiag = nullptr;
+
+  // level-ordered batches of the two triangular solves
+  int G = 64;  // lanes per row in the triangular solves
+  int32_t *ord_f = nullptr, *ord_b = nullptr;
+  int64_t nbatch_f = 0, nbatch_b = 0, nlev_f = 0, nlev_b = 0;
+
+  // float32 copy of A when A is stored in float64 (FP32_REFINE)
+  const float *A32 = nullptr;
+  float *A32own = nullptr;
+
+  // work vectors
+  double *vy = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vu = nullptr,
+         *vg = nullptr, *vrhs = nullptr, *vx = nullptr;
+  float *fy = nullptr, *fr = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr, *fu = nullptr,
+        *frhs = nullptr, *fe = nullptr;
+  double *part = nullptr;  // reduction partials / dense A^T(Ap) partial rows
+  size_t part_bytes = 0;
+  double *scal = nullptr;  // device scalars (float64)
+  float *scalf = nullptr;  // device scalars (float32)
+  int32_t *flags = nullptr;  // device status flags
+  double *hscal = nullptr;   // pinned host scalars
+  double *vm = nullptr;      // m-length float64 scratch
+
+  // sparse A^T(Ap) algorithm in use
+  int atap_algo = 1;
+
+  // kernel timing (opt.profile)
+  static constexpr int kProfSlots = 64;
+  hipEvent_t prof_ev[2 * kProfSlots] = {};
+  int prof_cls[kProfSlots] = {};
+  double prof_bytes[kProfSlots] = {};
+  int prof_used = 0;
+  bool prof_ready = false;
+  lsq_kernel_stats kstats{};
+
+  lsq_info info{};
+  std::string err;
+  std::vector<lsq::Dev> allocs;
+  bool solved = false;
+};
+
+namespace lsq {
+
+// ---------------------------------------------------------------------------
+// launchers (each enqueues on `st`; no host synchronisation)
+
+// setup (k_setup.hip)
+void launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
+void launch_fill_f32(float *x, int64_t n, float v, hipStream_t st);
+void launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t st);
+void launch_colnorm_dense(const lsq_ctx *c, double *part, int nblk, hipStream_t st);
+void launch_colnorm_csr(const lsq_ctx *c, double *sumsq, hipStream_t st);
+void launch_colnorm_finish(int64_t n, const double *part, int nblk, double *D, double *invD,
+                           float *invD32, int32_t *flags, hipStream_t st);
+void launch_rowweight(const lsq_ctx *c, double *w, int32_t *flags, hipStream_t st);
+void launch_scan_cdf(int64_t m, const double *w, double *cdf, double *blocksum, hipStream_t st);
+void launch_draw(int64_t m, const double *w, const double *cdf, int64_t s, uint64_t seed,
+                 int64_t *idx, double *gap, int32_t *cnt, hipStream_t st);
+// distinct rows: returns device count in *dcount (int64); urow/ucnt sized m
+void launch_compact_counts(int64_t m, const int32_t *cnt, int64_t *scratch, int64_t *urow,
+                           int32_t *ucnt, int64_t *dcount, hipStream_t st);
+size_t scan_scratch_elems(int64_t m);
+
+// Gram (k_gram.hip)
+// dense: gathers the scaled distinct rows into As (s_d x n, row-major) then
+// M = As^T As (upper tiles by MFMA, mirrored)
+void launch_gather_dense_f64(const lsq_ctx *c, double *As, hipStream_t st);
+void launch_gather_dense_f32(const lsq_ctx *c, float *As, hipStream_t st);
+void launch_syrk_f64(int64_t sd, int64_t n, const double *As, double *M, hipStream_t st);
+void launch_syrk_f32(int64_t sd, int64_t n, const float *As, float *M, hipStream_t st);
+void launch_dense_diag_guard_f64(int64_t n, double *M, int32_t *flags, hipStream_t st);
+void launch_dense_diag_guard_f32(int64_t n, float *M, int32_t *flags, hipStream_t st);
+// sparse Gram (several passes with host-read sizes); returns LSQ code
+int build_sparse_gram(lsq_ctx *c);
+void launch_cast_f64_f32(const double *x, float *y, int64_t n, hipStream_t st);
+
+// SGS (k_sgs.hip)
+int build_levels(lsq_ctx *c);
+void sgs_apply_f64(lsq_ctx *c, const double *r, double *z);
+void sgs_apply_f32(lsq_ctx *c, const float *r, float *z);
+
+// A^T(Ap) and friends (k_atap.hip)
+// q = s_out .* A^T( hb*b - A (s_in .* p) ), with hb in {0,1}; s_in/s_out may be null
+void atap_f64(lsq_ctx *c, const double *s_in, const double *p, const double *b, double *q,
+              const double *s_out);
+void atap_f32(lsq_ctx *c, const float *s_in, const float *p, float *q, const float *s_out);
+// float64 residual pass: g = A^T (b - A x) (b may be null: g = -A^T A x)
+void resid64(lsq_ctx *c, const double *x, const double *b, double *g);
+// backward pass over A: grad_b = A lam, grad_A = (b - A x) lam^T - (A lam) x^T
+void grad_pass(lsq_ctx *c, const double *x, const double *lam, double *grad_b, void *grad_A);
+
+// vector ops (k_vec.hip)
+template <typename T>
+struct Vec {
+  static void scale(int64_t n, const T *a, const T *x, T *y, hipStream_t st);  // y = a.*x
+  static void copy(int64_t n, const T *x, T *y, hipStream_t st);
+  // dot partials: part[nb] = partial sums of x.*y (or (d.*x)^2 when d != null and y == null)
+  static int dot_partials(int64_t n, const T *x, const T *y, const double *d, double *part,
+                          hipStream_t st);
+  // y += alpha p; r -= alpha q; partial sums of (d .* r)^2 (d may be null)
+  static int update_yr(int64_t n, const double *alpha, const T *p, const T *q, T *y, T *r,
+                       const double *d, double *part, hipStream_t st);
+  // p = z + beta p  (beta == null: p = z)
+  static void update_p(int64_t n, const double *beta, const T *z, T *p, hipStream_t st);
+};
+// single-block finisher over `np` partials (fixed order, deterministic):
+// op 0: scal[dst] = sum; op 1: scal[PQ] = sum, scal[ALPHA] = scal[RHO] / sum;
+// op 2: scal[RHO] = scal[RHO_NEW] = sum
+void launch_finish(const double *part, int np, double *scal, int dst, int op, hipStream_t st);
+// beta = scal[RHO_NEW] / scal[RHO]; scal[RHO] = scal[RHO_NEW]
+void launch_beta(double *scal, hipStream_t st);
+// x = a .* y in float64 (x = D^-1 y) and float32->float64 axpy helpers
+void launch_axpy_scaled_f64(int64_t n, double nu, const double *invD, const float *d, double *x,
+                            hipStream_t st);
+void launch_f64_to_f32_scaled(int64_t n, const double *x, const double *s, double mul, float *y,
+                              hipStream_t st);
+void launch_f32_to_f64(int64_t n, const float *x, double *y, hipStream_t st);
+void launch_sub_f64(int64_t n, const double *a, const double *b, double *y, hipStream_t st);
+
+}  // namespace lsq
+
+namespace lsq {
+// kernel timing around launches of one class; no-ops unless opt.profile
+int prof_begin(lsq_ctx *c, int cls);
+void prof_end(lsq_ctx *c, int slot, double bytes);
+void prof_harvest(lsq_ctx *c);  // call after the stream has been synchronised
+enum { KC_TRSV = 0, KC_SGS_RHS = 1, KC_ATAP = 2, KC_VEC = 3 };
+}  // namespace lsq
+
+#define LSQ_HIP_CHECK(expr)                                   \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return lsq_hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+int lsq_hip_fail(lsq_ctx *ctx, hipError_t e, const char *what);
+void *lsq_alloc(lsq_ctx *ctx, size_t bytes);

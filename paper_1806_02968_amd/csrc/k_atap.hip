@@ -1,0 +1,419 @@
+// The per-iteration product of Algorithm 2 step 4: only Ax and A^T(Ax) are
+// needed (Section 4.2), here fused into one pass over A. For each row a_i the
+// pass forms t_i = hb*b_i - a_i . u and accumulates t_i a_i^T into the output,
+// so A is read once per product:
+//   K p = D^{-1} A^T A D^{-1} p   (u = D^{-1} p, hb = 0, output scaled by D^{-1})
+//   g   = A^T (b - A x)           (u = x, hb = 1: the float64 refinement residual)
+//
+// Dense A (row-major): one wave per row; lane l holds columns l, l+64, ...,
+// so every load instruction moves 64 consecutive elements; the row dot is a
+// wave reduction and the rank-1 update stays in registers; each block writes
+// one partial output row and a second kernel sums the partial rows in a fixed
+// order.
+//
+// CSR A: G lanes per row; the scatter of t_i a_i goes to global memory with
+// atomic adds, or (n small enough) to a per-block LDS accumulator flushed
+// once per block.
+#include "common.h"
+
+namespace lsq {
+
+constexpr int kAtThreads = 256, kAtWaves = kAtThreads / kWave;
+
+template <typename TA, typename CT, int NC, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_atap_dense(int64_t m, int n, int64_t ld, const TA *__restrict__ A,
+                                                           const CT *__restrict__ u, const double *__restrict__ b,
+                                                           CT *__restrict__ part, int64_t rows_per_blk) {
+  __shared__ CT red[64 * NC];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  CT ur[NC], acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = lane + 64 * c;
+    ur[c] = j < n ? u[j] : (CT)0;
+    acc[c] = 0;
+  }
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  int64_t r1 = r0 + rows_per_blk;
+  if (r1 > m) r1 = m;
+  int64_t i = r0 + wave;
+  // two rows per step keep twice the loads in flight
+  for (; i + kAtWaves < r1; i += 2 * kAtWaves) {
+    const TA *row0 = A + i * ld;
+    const TA *row1 = A + (i + kAtWaves) * ld;
+    CT a0[NC], a1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      a0[c] = j < n ? (CT)row0[j] : (CT)0;
+      a1[c] = j < n ? (CT)row1[j] : (CT)0;
+    }
+    CT d0 = 0, d1 = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      d0 += a0[c] * ur[c];
+      d1 += a1[c] * ur[c];
+    }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
+    if (HAS_B) {
+      d0 = (CT)b[i] - d0;
+      d1 = (CT)b[i + kAtWaves] - d1;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += d0 * a0[c] + d1 * a1[c];
+  }
+  if (i < r1) {
+    const TA *row0 = A + i * ld;
+    CT a0[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = lane + 64 * c;
+      a0[c] = j < n ? (CT)row0[j] : (CT)0;
+    }
+    CT d0 = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) d0 += a0[c] * ur[c];
+    d0 = wave_sum(d0);
+    if (HAS_B) d0 = (CT)b[i] - d0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += d0 * a0[c];
+  }
+  // combine the four waves in a fixed order
+  for (int w = 0; w < kAtWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) red[lane + 64 * c] = (w == 0 ? (CT)0 : red[lane + 64 * c]) + acc[c];
+    }
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < n; j += kAtThreads) part[blockIdx.x * (int64_t)n + j] = red[j];
+}
+
+template <typename CT>
+__global__ void k_atap_finish(int64_t n, const CT *__restrict__ part, int nblk, const CT *__restrict__ s_out,
+                              CT *__restrict__ q) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    CT s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * n + j];
+    q[j] = s_out ? s * s_out[j] : s;
+  }
+}
+
+// generic dense fallback for n > 2048: y = hb*b - A u, then per-block column
+// partials of A^T y
+template <typename TA, typename CT, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_gemv_rows(int64_t m, int64_t n, int64_t ld, const TA *__restrict__ A,
+                                                          const CT *__restrict__ u, const double *__restrict__ b,
+                                                          CT *__restrict__ y) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t i = wave; i < m; i += nw) {
+    CT d = 0;
+    for (int64_t j = lane; j < n; j += 64) d += (CT)A[i * ld + j] * u[j];
+    d = wave_sum(d);
+    if (lane == 0) y[i] = HAS_B ? (CT)b[i] - d : d;
+  }
+}
+
+template <typename TA, typename CT>
+__global__ __launch_bounds__(kAtThreads) void k_gemv_t_part(int64_t m, int64_t n, int64_t ld, const TA *__restrict__ A,
+                                                            const CT *__restrict__ y, CT *__restrict__ part,
+                                                            int64_t rows_per_blk) {
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  int64_t r1 = r0 + rows_per_blk;
+  if (r1 > m) r1 = m;
+  for (int64_t j = threadIdx.x; j < n; j += kAtThreads) {
+    CT s = 0;
+    for (int64_t i = r0; i < r1; ++i) s += (CT)A[i * ld + j] * y[i];
+    part[blockIdx.x * n + j] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR
+
+template <typename TA, typename CT, int G, bool HAS_B, bool LDS>
+__global__ __launch_bounds__(kAtThreads) void k_atap_csr(int64_t m, int n, const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci, const TA *__restrict__ v,
+                                                         const CT *__restrict__ u, const double *__restrict__ b,
+                                                         CT *__restrict__ q, int64_t rows_per_blk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  CT *qs = (CT *)smem;
+  if (LDS) {
+    for (int j = threadIdx.x; j < n; j += kAtThreads) qs[j] = 0;
+    __syncthreads();
+  }
+  const int gl = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = kAtThreads / G;
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  int64_t r1 = r0 + rows_per_blk;
+  if (r1 > m) r1 = m;
+  const int64_t iters = (rows_per_blk + ngrp - 1) / ngrp;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = r0 + grp + it * ngrp;
+    CT d = 0;
+    int64_t k0 = 0, k1 = 0;
+    if (i < r1) {
+      k0 = rp[i];
+      k1 = rp[i + 1];
+      for (int64_t k = k0 + gl; k < k1; k += G) d += (CT)v[k] * u[ci[k]];
+    }
+    d = group_sum<G>(d);
+    if (HAS_B && i < r1) d = (CT)b[i] - d;
+    if (i < r1) {
+      for (int64_t k = k0 + gl; k < k1; k += G) {
+        const CT add = d * (CT)v[k];
+        if (LDS) atomicAdd(&qs[ci[k]], add);
+        else atomicAdd(&q[ci[k]], add);
+      }
+    }
+  }
+  if (LDS) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kAtThreads) {
+      const CT s = qs[j];
+      if (s != (CT)0) atomicAdd(&q[j], s);
+    }
+  }
+}
+
+template <typename CT>
+__global__ void k_scale_inplace(int64_t n, const CT *__restrict__ s, CT *__restrict__ q) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    q[j] *= s[j];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+
+void atap_f64_impl(lsq_ctx *c, const double *s_in, const double *p, const double *b, double *q,
+                   const double *s_out);
+
+static int dense_blocks(int64_t m) {
+  int64_t b = m / 64;
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+template <typename TA, typename CT, bool HAS_B>
+static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, CT *q, const CT *s_out) {
+  const int64_t m = c->m, n = c->n;
+  const int nblk = dense_blocks(m);
+  const int64_t rpb = (m + nblk - 1) / nblk;
+  CT *part = (CT *)c->part;
+  hipStream_t st = c->stream;
+  const int nb = (int)n;
+  if (n <= 64) k_atap_dense<TA, CT, 1, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else if (n <= 128) k_atap_dense<TA, CT, 2, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else if (n <= 256) k_atap_dense<TA, CT, 4, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else if (n <= 512) k_atap_dense<TA, CT, 8, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else if (n <= 1024) k_atap_dense<TA, CT, 16, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else if (n <= 2048) k_atap_dense<TA, CT, 32, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+  else {
+    CT *y = (CT *)c->vm;
+    k_gemv_rows<TA, CT, HAS_B><<<8192, kAtThreads, 0, st>>>(m, n, c->ld, A, u, b, y);
+    k_gemv_t_part<TA, CT><<<nblk, kAtThreads, 0, st>>>(m, n, c->ld, A, y, part, rpb);
+  }
+  int64_t fb = (n + 255) / 256;
+  k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part, nblk, s_out, q);
+}
+
+template <typename TA, typename CT, bool HAS_B, int G>
+static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, bool lds) {
+  const int64_t m = c->m;
+  const int n = (int)c->n;
+  hipStream_t st = c->stream;
+  if (lds) {
+    const int64_t nblk = 512;
+    const int64_t rpb = (m + nblk - 1) / nblk;
+    auto kern = k_atap_csr<TA, CT, G, HAS_B, true>;
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr = true;
+    }
+    kern<<<(unsigned)nblk, kAtThreads, (size_t)n * sizeof(CT), st>>>(m, n, c->rp, c->ci, v, u, b, q, rpb);
+  } else {
+    const int64_t rows_per_grp_iter = kAtThreads / G;
+    int64_t nblk = (m + rows_per_grp_iter * 4 - 1) / (rows_per_grp_iter * 4);
+    if (nblk > 65536) nblk = 65536;
+    if (nblk < 1) nblk = 1;
+    const int64_t rpb = (m + nblk - 1) / nblk;
+    k_atap_csr<TA, CT, G, HAS_B, false><<<(unsigned)nblk, kAtThreads, 0, st>>>(m, n, c->rp, c->ci, v, u, b, q, rpb);
+  }
+}
+
+template <typename TA, typename CT, bool HAS_B>
+static void atap_csr_t(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, const CT *s_out) {
+  hipStream_t st = c->stream;
+  if (sizeof(CT) == 8) launch_fill_f64((double *)q, c->n, 0.0, st);
+  else launch_fill_f32((float *)q, c->n, 0.0f, st);
+  const bool lds = c->atap_algo == 2 && c->n * (int64_t)sizeof(CT) <= 131072;
+  const double avg = (double)c->nnz / (double)c->m;
+  if (avg <= 2) atap_csr_g<TA, CT, HAS_B, 2>(c, v, u, b, q, lds);
+  else if (avg <= 4) atap_csr_g<TA, CT, HAS_B, 4>(c, v, u, b, q, lds);
+  else if (avg <= 8) atap_csr_g<TA, CT, HAS_B, 8>(c, v, u, b, q, lds);
+  else if (avg <= 16) atap_csr_g<TA, CT, HAS_B, 16>(c, v, u, b, q, lds);
+  else if (avg <= 32) atap_csr_g<TA, CT, HAS_B, 32>(c, v, u, b, q, lds);
+  else atap_csr_g<TA, CT, HAS_B, 64>(c, v, u, b, q, lds);
+  if (s_out) {
+    int64_t fb = (c->n + 255) / 256;
+    k_scale_inplace<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(c->n, s_out, q);
+  }
+}
+
+// algorithmic bytes of one fused pass: every stored entry of A once (value,
+// plus column index and row pointers for CSR), the input vector, b when used,
+// and the output vector
+static double atap_bytes(const lsq_ctx *c, size_t ta, size_t ct, bool has_b) {
+  const double n = (double)c->n, m = (double)c->m;
+  double by = 2 * n * ct + (has_b ? 8 * m : 0);
+  if (c->fmt == LSQ_DENSE) by += m * n * ta;
+  else by += (double)c->nnz * (ta + 4) + (m + 1) * 8;
+  return by;
+}
+
+void atap_f64(lsq_ctx *c, const double *s_in, const double *p, const double *b, double *q, const double *s_out) {
+  const int slot = prof_begin(c, KC_ATAP);
+  atap_f64_impl(c, s_in, p, b, q, s_out);
+  prof_end(c, slot, atap_bytes(c, c->dtype == LSQ_F64 ? 8 : 4, 8, b != nullptr));
+}
+
+void atap_f64_impl(lsq_ctx *c, const double *s_in, const double *p, const double *b, double *q,
+                   const double *s_out) {
+  const double *u = p;
+  if (s_in) {
+    Vec<double>::scale(c->n, s_in, p, c->vu, c->stream);
+    u = c->vu;
+  }
+  if (c->fmt == LSQ_DENSE) {
+    if (c->dtype == LSQ_F64) {
+      if (b) atap_dense_t<double, double, true>(c, (const double *)c->A, u, b, q, s_out);
+      else atap_dense_t<double, double, false>(c, (const double *)c->A, u, b, q, s_out);
+    } else {
+      if (b) atap_dense_t<float, double, true>(c, (const float *)c->A, u, b, q, s_out);
+      else atap_dense_t<float, double, false>(c, (const float *)c->A, u, b, q, s_out);
+    }
+  } else {
+    if (c->dtype == LSQ_F64) {
+      if (b) atap_csr_t<double, double, true>(c, (const double *)c->A, u, b, q, s_out);
+      else atap_csr_t<double, double, false>(c, (const double *)c->A, u, b, q, s_out);
+    } else {
+      if (b) atap_csr_t<float, double, true>(c, (const float *)c->A, u, b, q, s_out);
+      else atap_csr_t<float, double, false>(c, (const float *)c->A, u, b, q, s_out);
+    }
+  }
+}
+
+void atap_f32(lsq_ctx *c, const float *s_in, const float *p, float *q, const float *s_out) {
+  const int slot = prof_begin(c, KC_ATAP);
+  const float *u = p;
+  if (s_in) {
+    Vec<float>::scale(c->n, s_in, p, c->fu, c->stream);
+    u = c->fu;
+  }
+  if (c->fmt == LSQ_DENSE) atap_dense_t<float, float, false>(c, c->A32, u, nullptr, q, s_out);
+  else atap_csr_t<float, float, false>(c, c->A32, u, nullptr, q, s_out);
+  prof_end(c, slot, atap_bytes(c, 4, 4, false));
+}
+
+void resid64(lsq_ctx *c, const double *x, const double *b, double *g) {
+  if (b) {
+    atap_f64(c, nullptr, x, b, g, nullptr);
+  } else {
+    atap_f64(c, nullptr, x, nullptr, g, nullptr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward pass over A
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_grad_dense(int64_t m, int64_t n, int64_t ld, const TA *__restrict__ A,
+                                                    const double *__restrict__ b, const double *__restrict__ x,
+                                                    const double *__restrict__ lam, double *__restrict__ gb,
+                                                    TA *__restrict__ gA) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t i = wave; i < m; i += nw) {
+    const TA *row = A + i * ld;
+    double dv = 0, dx = 0;
+    for (int64_t j = lane; j < n; j += 64) {
+      const double a = (double)row[j];
+      dv += a * lam[j];
+      dx += a * x[j];
+    }
+    dv = wave_sum(dv);
+    dx = wave_sum(dx);
+    const double ri = b[i] - dx;
+    if (gb && lane == 0) gb[i] = dv;
+    if (gA)
+      for (int64_t j = lane; j < n; j += 64) gA[i * ld + j] = (TA)(ri * lam[j] - dv * x[j]);
+  }
+}
+
+template <typename TA, int G>
+__global__ __launch_bounds__(256) void k_grad_csr(int64_t m, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const TA *__restrict__ v,
+                                                  const double *__restrict__ b, const double *__restrict__ x,
+                                                  const double *__restrict__ lam, double *__restrict__ gb,
+                                                  TA *__restrict__ gA) {
+  const int gl = threadIdx.x % G;
+  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int64_t iters = (m + ngrp - 1) / ngrp;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = grp + it * ngrp;
+    double dv = 0, dx = 0;
+    if (i < m)
+      for (int64_t k = rp[i] + gl; k < rp[i + 1]; k += G) {
+        const double a = (double)v[k];
+        dv += a * lam[ci[k]];
+        dx += a * x[ci[k]];
+      }
+    dv = group_sum<G>(dv);
+    dx = group_sum<G>(dx);
+    if (i < m) {
+      const double ri = b[i] - dx;
+      if (gb && gl == 0) gb[i] = dv;
+      if (gA)
+        for (int64_t k = rp[i] + gl; k < rp[i + 1]; k += G) gA[k] = (TA)(ri * lam[ci[k]] - dv * x[ci[k]]);
+    }
+  }
+}
+
+template <typename TA>
+static void grad_t(lsq_ctx *c, const double *x, const double *lam, double *gb, TA *gA) {
+  hipStream_t st = c->stream;
+  if (c->fmt == LSQ_DENSE) {
+    int64_t blk = (c->m * 64 + 255) / 256;
+    if (blk > 16384) blk = 16384;
+    k_grad_dense<TA><<<(unsigned)blk, 256, 0, st>>>(c->m, c->n, c->ld, (const TA *)c->A, c->b, x, lam, gb, gA);
+  } else {
+    const double avg = (double)c->nnz / (double)c->m;
+    const int64_t G = avg <= 2 ? 2 : avg <= 4 ? 4 : avg <= 8 ? 8 : avg <= 16 ? 16 : avg <= 32 ? 32 : 64;
+    int64_t blk = (c->m * G + 255) / 256;
+    if (blk > 16384) blk = 16384;
+    const TA *v = (const TA *)c->A;
+    switch (G) {
+      case 2: k_grad_csr<TA, 2><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+      case 4: k_grad_csr<TA, 4><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+      case 8: k_grad_csr<TA, 8><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+      case 16: k_grad_csr<TA, 16><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+      case 32: k_grad_csr<TA, 32><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+      default: k_grad_csr<TA, 64><<<(unsigned)blk, 256, 0, st>>>(c->m, c->rp, c->ci, v, c->b, x, lam, gb, gA); break;
+    }
+  }
+}
+
+void grad_pass(lsq_ctx *c, const double *x, const double *lam, double *grad_b, void *grad_A) {
+  if (c->dtype == LSQ_F64) grad_t<double>(c, x, lam, grad_b, (double *)grad_A);
+  else grad_t<float>(c, x, lam, grad_b, (float *)grad_A);
+}
+
+}  // namespace lsq

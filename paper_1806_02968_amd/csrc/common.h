@@ -32,6 +32,38 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Sums over groups of G lanes with DPP moves (no LDS traffic). G <= 16: every
+// lane of the group holds the sum; G == 32: lane 31 of each half-wave; G == 64:
+// lane 63. dpp_sum_lane<G>() names a lane holding the result.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int tlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, false);
+  const int thi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(thi, tlo);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_take(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T dpp_group_sum(T v) {
+  // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror
+  if (G >= 2) v += dpp_take<0xB1, 0xF>(v);
+  if (G >= 4) v += dpp_take<0x4E, 0xF>(v);
+  if (G >= 8) v += dpp_take<0x141, 0xF>(v);
+  if (G >= 16) v += dpp_take<0x140, 0xF>(v);
+  // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2 and 3
+  if (G >= 32) v += dpp_take<0x142, 0xA>(v);
+  if (G >= 64) v += dpp_take<0x143, 0xC>(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int dpp_sum_lane() {
+  return G == 64 ? 63 : (G == 32 ? 31 : 0);
+}
+
 // block-wide sum, result valid in every thread; red must hold blockDim/64 T
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T *red) {
@@ -98,6 +130,7 @@ struct lsq_ctx {
   // level-ordered batches of the two triangular solves
   int G = 64;  // lanes per row in the triangular solves
   int32_t *ord_f = nullptr, *ord_b = nullptr;
+  int4 *task_f = nullptr, *task_b = nullptr;  // CSR: (row, k0, k1, diag) per slot
   int64_t nbatch_f = 0, nbatch_b = 0, nlev_f = 0, nlev_b = 0;
 
   // float32 copy of A when A is stored in float64 (FP32_REFINE)

@@ -14,6 +14,8 @@
 // CSR A: G lanes per row; the scatter of t_i a_i goes to global memory with
 // atomic adds, or (n small enough) to a per-block LDS accumulator flushed
 // once per block.
+#include <algorithm>
+
 #include "common.h"
 
 namespace lsq {
@@ -88,6 +90,20 @@ __global__ __launch_bounds__(kAtThreads) void k_atap_dense(int64_t m, int n, int
     __syncthreads();
   }
   for (int j = threadIdx.x; j < n; j += kAtThreads) part[blockIdx.x * (int64_t)n + j] = red[j];
+}
+
+// first level of the partial-row reduction: blockIdx.y sums rows
+// [y*seg, (y+1)*seg) of part into row y of out (fixed order)
+template <typename CT>
+__global__ void k_part_reduce(int64_t n, const CT *__restrict__ part, int nblk, int seg, CT *__restrict__ out) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int b0 = blockIdx.y * seg;
+  int b1 = b0 + seg;
+  if (b1 > nblk) b1 = nblk;
+  CT s = 0;
+  for (int b = b0; b < b1; ++b) s += part[(int64_t)b * n + j];
+  out[blockIdx.y * n + j] = s;
 }
 
 template <typename CT>
@@ -180,6 +196,50 @@ __global__ __launch_bounds__(kAtThreads) void k_atap_csr(int64_t m, int n, const
   }
 }
 
+// per-workgroup accumulation in LDS; each workgroup writes one partial output
+// row, summed over workgroups in a fixed order by k_atap_finish
+constexpr int kLdsThreads = 1024, kLdsBlocks = 256;
+
+template <typename TA, typename CT, int G, bool HAS_B, bool USTAGE>
+__global__ __launch_bounds__(kLdsThreads) void k_atap_csr_lds(int64_t m, int n, const int64_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ ci,
+                                                              const TA *__restrict__ v, const CT *__restrict__ ug,
+                                                              const double *__restrict__ b, CT *__restrict__ part,
+                                                              int64_t rows_per_blk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  CT *qs = (CT *)smem;
+  CT *us = qs + n;  // a copy of u when it fits beside the accumulator
+  for (int j = threadIdx.x; j < n; j += kLdsThreads) {
+    qs[j] = 0;
+    if (USTAGE) us[j] = ug[j];
+  }
+  __syncthreads();
+  const CT *u = USTAGE ? us : ug;
+  const int gl = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  constexpr int ngrp = kLdsThreads / G;
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  int64_t r1 = r0 + rows_per_blk;
+  if (r1 > m) r1 = m;
+  const int64_t iters = (rows_per_blk + ngrp - 1) / ngrp;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = r0 + grp + it * ngrp;
+    CT d = 0;
+    int64_t k0 = 0, k1 = 0;
+    if (i < r1) {
+      k0 = rp[i];
+      k1 = rp[i + 1];
+      for (int64_t k = k0 + gl; k < k1; k += G) d += (CT)v[k] * u[ci[k]];
+    }
+    d = group_sum<G>(d);
+    if (HAS_B && i < r1) d = (CT)b[i] - d;
+    if (i < r1)
+      for (int64_t k = k0 + gl; k < k1; k += G) atomicAdd(&qs[ci[k]], d * (CT)v[k]);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += kLdsThreads) part[blockIdx.x * (int64_t)n + j] = qs[j];
+}
+
 template <typename CT>
 __global__ void k_scale_inplace(int64_t n, const CT *__restrict__ s, CT *__restrict__ q) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
@@ -218,8 +278,12 @@ static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, 
     k_gemv_rows<TA, CT, HAS_B><<<8192, kAtThreads, 0, st>>>(m, n, c->ld, A, u, b, y);
     k_gemv_t_part<TA, CT><<<nblk, kAtThreads, 0, st>>>(m, n, c->ld, A, y, part, rpb);
   }
-  int64_t fb = (n + 255) / 256;
-  k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part, nblk, s_out, q);
+  const int seg = 16;
+  const int nseg = (nblk + seg - 1) / seg;
+  CT *part2 = part + (int64_t)nblk * n;
+  const int64_t fb = (n + 255) / 256;
+  k_part_reduce<CT><<<dim3((unsigned)(fb > 0 ? fb : 1), (unsigned)nseg), 256, 0, st>>>(n, part, nblk, seg, part2);
+  k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part2, nseg, s_out, q);
 }
 
 template <typename TA, typename CT, bool HAS_B, int G>
@@ -228,15 +292,28 @@ static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
   const int n = (int)c->n;
   hipStream_t st = c->stream;
   if (lds) {
-    const int64_t nblk = 512;
+    const int64_t nblk = std::min<int64_t>(kLdsBlocks, std::max<int64_t>(1, m / 64));
     const int64_t rpb = (m + nblk - 1) / nblk;
-    auto kern = k_atap_csr<TA, CT, G, HAS_B, true>;
+    const bool ustage = 2 * (int64_t)n * (int64_t)sizeof(CT) <= 160 * 1024;
+    auto kern = ustage ? k_atap_csr_lds<TA, CT, G, HAS_B, true> : k_atap_csr_lds<TA, CT, G, HAS_B, false>;
     static bool attr = false;
     if (!attr) {
-      (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute((const void *)k_atap_csr_lds<TA, CT, G, HAS_B, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute((const void *)k_atap_csr_lds<TA, CT, G, HAS_B, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       attr = true;
     }
-    kern<<<(unsigned)nblk, kAtThreads, (size_t)n * sizeof(CT), st>>>(m, n, c->rp, c->ci, v, u, b, q, rpb);
+    CT *part = (CT *)c->part;
+    const size_t lds = (size_t)n * sizeof(CT) * (ustage ? 2 : 1);
+    kern<<<(unsigned)nblk, kLdsThreads, lds, st>>>(m, n, c->rp, c->ci, v, u, b, part, rpb);
+    // partial rows: 16-row segments in parallel, then the segment sums
+    const int seg = 16;
+    const int nseg = (int)((nblk + seg - 1) / seg);
+    CT *part2 = part + nblk * (int64_t)n;
+    const int64_t fb = (n + 255) / 256;
+    k_part_reduce<CT><<<dim3((unsigned)(fb > 0 ? fb : 1), (unsigned)nseg), 256, 0, st>>>(n, part, (int)nblk, seg, part2);
+    k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part2, nseg, nullptr, q);
   } else {
     const int64_t rows_per_grp_iter = kAtThreads / G;
     int64_t nblk = (m + rows_per_grp_iter * 4 - 1) / (rows_per_grp_iter * 4);
@@ -250,9 +327,11 @@ static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
 template <typename TA, typename CT, bool HAS_B>
 static void atap_csr_t(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, const CT *s_out) {
   hipStream_t st = c->stream;
-  if (sizeof(CT) == 8) launch_fill_f64((double *)q, c->n, 0.0, st);
-  else launch_fill_f32((float *)q, c->n, 0.0f, st);
-  const bool lds = c->atap_algo == 2 && c->n * (int64_t)sizeof(CT) <= 131072;
+  const bool lds = c->atap_algo == 2;
+  if (!lds) {
+    if (sizeof(CT) == 8) launch_fill_f64((double *)q, c->n, 0.0, st);
+    else launch_fill_f32((float *)q, c->n, 0.0f, st);
+  }
   const double avg = (double)c->nnz / (double)c->m;
   if (avg <= 2) atap_csr_g<TA, CT, HAS_B, 2>(c, v, u, b, q, lds);
   else if (avg <= 4) atap_csr_g<TA, CT, HAS_B, 4>(c, v, u, b, q, lds);

@@ -44,12 +44,47 @@ __device__ __forceinline__ typename Bits<T>::U to_bits(T v) {
 constexpr int kTrsvThreads = 1024, kTrsvWaves = kTrsvThreads / kWave;
 constexpr int kSpinLimit = 1 << 24;
 
-template <typename T, bool DENSE, bool UPPER, bool LDSX, int G>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int32_t *__restrict__ rp,
+// One row of a solve: the row, its entry range [k0, k1) in the triangle being
+// solved (CSR positions, or positions in the dense row-major M) and the
+// position of its diagonal.
+struct RowTask {
+  int row;
+  int64_t k0, k1, dpos;
+};
+
+template <bool DENSE, bool UPPER, int R>
+__device__ __forceinline__ RowTask get_task(int b, int g, int nbatch, int n, const int4 *__restrict__ task,
+                                            const int32_t *__restrict__ ord) {
+  RowTask t{-1, 0, 0, 0};
+  if (b >= nbatch) return t;
+  if (DENSE) {
+    const int row = ord[b * R + g];
+    t.row = row;
+    if (row >= 0) {
+      const int64_t base = (int64_t)row * n;
+      t.dpos = base + row;
+      t.k0 = UPPER ? t.dpos + 1 : base;
+      t.k1 = UPPER ? base + n : t.dpos;
+    }
+  } else {
+    const int4 q = task[b * R + g];
+    t.row = q.x;
+    t.k0 = q.y;
+    t.k1 = q.z;
+    t.dpos = q.w;
+  }
+  return t;
+}
+
+// E entries per lane are loaded into registers in one burst (G*E per row per
+// chunk); the next batch's row is loaded while the current row waits for its
+// dependencies, so the global-memory latency overlaps the dependency chain.
+template <typename T, bool DENSE, bool UPPER, bool LDSX, int G, int E>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__restrict__ task,
+                                                       const int32_t *__restrict__ ord,
                                                        const int32_t *__restrict__ ci, const T *__restrict__ val,
-                                                       const int32_t *__restrict__ dg, const T *__restrict__ rhs,
-                                                       T *__restrict__ x, const int32_t *__restrict__ ord,
-                                                       int nbatch, int32_t *__restrict__ err) {
+                                                       const T *__restrict__ rhs, T *__restrict__ x, int nbatch,
+                                                       int32_t *__restrict__ err) {
   typedef typename Bits<T>::U U;
   constexpr int R = kWave / G;
   constexpr int scope = LDSX ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
@@ -59,46 +94,91 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int32_t *__r
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int g = lane / G, gl = lane % G;
-  for (int b = wave; b < nbatch; b += kTrsvWaves) {
-    const int row = ord[b * R + g];
-    T acc = 0;
-    int64_t dpos = 0;
-    if (row >= 0) {
-      int64_t k0, k1;
-      if (DENSE) {
-        const int64_t base = (int64_t)row * n;
-        dpos = base + row;
-        k0 = UPPER ? dpos + 1 : base;
-        k1 = UPPER ? base + n : dpos;
+  bool failed = false;
+
+  auto load = [&](const RowTask &t, int64_t kb, int (&jj)[E], T (&vv)[E]) {
+    const int64_t base = DENSE && t.row >= 0 ? (int64_t)t.row * n : 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t k = kb + gl + (int64_t)G * e;
+      if (t.row >= 0 && k < t.k1) {
+        jj[e] = DENSE ? (int)(k - base) : ci[k];
+        vv[e] = val[k];
       } else {
-        dpos = dg[row];
-        k0 = UPPER ? dpos + 1 : rp[row];
-        k1 = UPPER ? rp[row + 1] : dpos;
-      }
-      const int64_t base = DENSE ? (int64_t)row * n : 0;
-      for (int64_t k = k0 + gl; k < k1; k += G) {
-        const int j = DENSE ? (int)(k - base) : ci[k];
-        const T v = val[k];
-        U u;
-        // bounded wait: a schedule error becomes a reported failure, never a hang
-        int spins = 0;
-        do {
-          u = __hip_atomic_load(&xs[j], __ATOMIC_RELAXED, scope);
-          if (++spins > kSpinLimit) {
-            atomicOr(err, 1);
-            u = 0;
-            break;
-          }
-        } while (u == Bits<T>::kSent);
-        acc += v * from_bits<T>(u);
+        jj[e] = -1;
+        vv[e] = 0;
       }
     }
-    acc = group_sum<G>(acc);
-    if (row >= 0 && gl == 0) {
-      const T xi = (rhs[row] - acc) / val[dpos];
-      __hip_atomic_store(&xs[row], to_bits<T>(xi), __ATOMIC_RELAXED, scope);
+  };
+  // all E reads are issued together; only entries still holding the sentinel
+  // are read again
+  auto consume = [&](const int (&jj)[E], const T (&vv)[E], T acc) -> T {
+    U u[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = jj[e] >= 0 ? __hip_atomic_load(&xs[jj[e]], __ATOMIC_RELAXED, scope) : (U)0;
+    int spins = 0;  // bounded wait: a schedule error is reported, never a hang
+    bool pending = true;
+    while (pending) {
+      pending = false;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (u[e] == Bits<T>::kSent) {
+          u[e] = __hip_atomic_load(&xs[jj[e]], __ATOMIC_RELAXED, scope);
+          pending = pending || (u[e] == Bits<T>::kSent);
+        }
+      if (pending && ++spins > kSpinLimit) {
+        failed = true;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (u[e] == Bits<T>::kSent) u[e] = 0;
+        pending = false;
+      }
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc += vv[e] * from_bits<T>(u[e]);
+    return acc;
+  };
+
+  // the task records run two rows ahead of the data, so the data loads of the
+  // next row never wait for their own task record
+  int b = wave;
+  RowTask cur = get_task<DENSE, UPPER, R>(b, g, nbatch, n, task, ord);
+  RowTask nx = get_task<DENSE, UPPER, R>(b + kTrsvWaves, g, nbatch, n, task, ord);
+  int cj[E];
+  T cv[E];
+  load(cur, cur.k0, cj, cv);
+  T crhs = cur.row >= 0 ? rhs[cur.row] : (T)0, cdg = cur.row >= 0 ? val[cur.dpos] : (T)1;
+  for (; b < nbatch; b += kTrsvWaves) {
+    const RowTask nx2 = get_task<DENSE, UPPER, R>(b + 2 * kTrsvWaves, g, nbatch, n, task, ord);
+    // prefetch the wave's next row
+    int nj[E];
+    T nv[E];
+    load(nx, nx.k0, nj, nv);
+    const T nrhs = nx.row >= 0 ? rhs[nx.row] : (T)0, ndg = nx.row >= 0 ? val[nx.dpos] : (T)1;
+
+    T acc = consume(cj, cv, (T)0);
+    for (int64_t kb = cur.k0 + (int64_t)G * E; kb < cur.k1; kb += (int64_t)G * E) {  // long rows
+      int tj[E];
+      T tv[E];
+      load(cur, kb, tj, tv);
+      acc = consume(tj, tv, acc);
+    }
+    acc = dpp_group_sum<G>(acc);
+    if (cur.row >= 0 && gl == dpp_sum_lane<G>()) {
+      const T xi = (crhs - acc) / cdg;
+      __hip_atomic_store(&xs[cur.row], to_bits<T>(xi), __ATOMIC_RELAXED, scope);
+    }
+    cur = nx;
+    nx = nx2;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      cj[e] = nj[e];
+      cv[e] = nv[e];
+    }
+    crhs = nrhs;
+    cdg = ndg;
   }
+  if (failed) atomicOr(err, 1);
   if (LDSX) {
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = from_bits<T>(xs[i]);
@@ -145,6 +225,7 @@ __global__ __launch_bounds__(256) void k_sgs_rhs(int n, const int32_t *__restric
 int build_levels(lsq_ctx *ctx) {
   const int64_t n = ctx->n;
   std::vector<int32_t> lev_f(n, 0), lev_b(n, 0);
+  std::vector<int32_t> rp_h, dg_h;
   if (ctx->Mdense) {
     for (int64_t i = 0; i < n; ++i) {
       lev_f[i] = (int32_t)i;
@@ -152,7 +233,10 @@ int build_levels(lsq_ctx *ctx) {
     }
     ctx->G = 64;
   } else {
-    std::vector<int32_t> rp(n + 1), ci(ctx->nnzM), dg(n);
+    std::vector<int32_t> &rp = rp_h, &dg = dg_h;
+    rp.resize(n + 1);
+    dg.resize(n);
+    std::vector<int32_t> ci(ctx->nnzM);
     LSQ_HIP_CHECK(hipMemcpyAsync(rp.data(), ctx->Mrp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     LSQ_HIP_CHECK(hipMemcpyAsync(ci.data(), ctx->Mci, ctx->nnzM * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     LSQ_HIP_CHECK(hipMemcpyAsync(dg.data(), ctx->Mdiag, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -194,6 +278,30 @@ int build_levels(lsq_ctx *ctx) {
   std::vector<int32_t> of, ob;
   order(lev_f, false, &ctx->nlev_f, &ctx->nbatch_f, of);
   order(lev_b, true, &ctx->nlev_b, &ctx->nbatch_b, ob);
+  if (!ctx->Mdense) {
+    // per-row tasks in level order: row, entry range of its triangle, diagonal
+    auto tasks = [&](const std::vector<int32_t> &ord, bool upper, int4 **out) -> int {
+      std::vector<int4> t(ord.size());
+      for (size_t q = 0; q < ord.size(); ++q) {
+        const int32_t i = ord[q];
+        if (i < 0) {
+          t[q] = make_int4(-1, 0, 0, 0);
+        } else if (upper) {
+          t[q] = make_int4(i, dg_h[i] + 1, rp_h[i + 1], dg_h[i]);
+        } else {
+          t[q] = make_int4(i, rp_h[i], dg_h[i], dg_h[i]);
+        }
+      }
+      *out = (int4 *)lsq_alloc(ctx, t.size() * sizeof(int4) + 16);
+      if (!*out) return LSQ_ENOMEM;
+      LSQ_HIP_CHECK(hipMemcpy(*out, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+      return LSQ_OK;
+    };
+    int rc = tasks(of, false, &ctx->task_f);
+    if (rc != LSQ_OK) return rc;
+    rc = tasks(ob, true, &ctx->task_b);
+    if (rc != LSQ_OK) return rc;
+  }
   ctx->ord_f = (int32_t *)lsq_alloc(ctx, of.size() * sizeof(int32_t) + 4);
   ctx->ord_b = (int32_t *)lsq_alloc(ctx, ob.size() * sizeof(int32_t) + 4);
   if (!ctx->ord_f || !ctx->ord_b) return LSQ_ENOMEM;
@@ -213,7 +321,8 @@ static bool lds_fits(int64_t n) {
 
 template <typename T, bool DENSE, bool UPPER, bool LDSX, int G>
 static void launch_trsv_g(lsq_ctx *c, const T *val, const T *rhs, T *x) {
-  auto kern = k_trsv<T, DENSE, UPPER, LDSX, G>;
+  constexpr int E = G >= 32 ? 8 : 4;
+  auto kern = k_trsv<T, DENSE, UPPER, LDSX, G, E>;
   size_t lds = LDSX ? (size_t)c->n * sizeof(T) : 0;
   static bool attr_set = false;
   if (LDSX && !attr_set) {
@@ -222,8 +331,8 @@ static void launch_trsv_g(lsq_ctx *c, const T *val, const T *rhs, T *x) {
   }
   const int32_t *ord = UPPER ? c->ord_b : c->ord_f;
   const int nb = (int)(UPPER ? c->nbatch_b : c->nbatch_f);
-  kern<<<1, kTrsvThreads, lds, c->stream>>>((int)c->n, c->Mrp, c->Mci, val, c->Mdiag, rhs, x, ord, nb,
-                                             c->flags + 3);
+  const int4 *task = UPPER ? c->task_b : c->task_f;
+  kern<<<1, kTrsvThreads, lds, c->stream>>>((int)c->n, task, ord, c->Mci, val, rhs, x, nb, c->flags + 3);
 }
 
 template <typename T, bool DENSE, bool UPPER, bool LDSX>

@@ -247,7 +247,12 @@ static int setup_impl(lsq_ctx *ctx) {
   ALLOC(ctx->w, double, m);
   ALLOC(ctx->cdf, double, m);
   // reduction partials and dense A^T(Ap) partial rows
-  const int64_t part_elems = std::max<int64_t>(ctx->fmt == LSQ_DENSE ? 1024 * n : n, 4096);
+  // sparse A^T(Ap): per-workgroup LDS partial rows when a row of n values fits
+  // in LDS, global atomics otherwise
+  if (ctx->opt.atap_algo == 0) ctx->atap_algo = n * 8 <= 131072 ? 2 : 1;
+  if (ctx->atap_algo == 2 && n * 8 > 131072) ctx->atap_algo = 1;
+  const int64_t part_elems = std::max<int64_t>(
+      ctx->fmt == LSQ_DENSE ? (1024 + 64) * n : (ctx->atap_algo == 2 ? (256 + 16) * n : n), 4096);
   ALLOC(ctx->part, double, part_elems);
   ctx->part_bytes = part_elems * sizeof(double);
   if (ctx->fmt == LSQ_DENSE && n > 2048) ALLOC(ctx->vm, double, m);
@@ -438,7 +443,7 @@ extern "C" int lsq_setup(const lsq_matrix *A, const double *b, double C, int32_t
   ctx->C = C;
   ctx->sweeps = sweeps;
   ctx->seed = seed;
-  ctx->atap_algo = o.atap_algo == 0 ? 1 : o.atap_algo;
+  ctx->atap_algo = o.atap_algo;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
     return LSQ_EHIP;

@@ -300,8 +300,10 @@ static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
     if (!attr) {
       (void)hipFuncSetAttribute((const void *)k_atap_csr_lds<TA, CT, G, HAS_B, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
       (void)hipFuncSetAttribute((const void *)k_atap_csr_lds<TA, CT, G, HAS_B, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
       attr = true;
     }
     CT *part = (CT *)c->part;

@@ -32,7 +32,7 @@ void *lsq_alloc(lsq_ctx *ctx, size_t bytes) {
   return p;
 }
 
-static void lsq_free_one(lsq_ctx *ctx, void *p) {
+void lsq_free_one(lsq_ctx *ctx, void *p) {
   for (size_t i = 0; i < ctx->allocs.size(); ++i)
     if (ctx->allocs[i].p == p) {
       (void)hipFree(p);

@@ -94,6 +94,14 @@ struct Scal {
 
 }  // namespace lsq
 
+// device-side tasks and entries of one triangular solve
+struct TriDev {
+  int4 *ta = nullptr, *tb = nullptr, *ft = nullptr;
+  int32_t *mci = nullptr, *fci = nullptr;
+  void *mval = nullptr, *fval = nullptr;
+  int64_t nbatch = 0, nft = 0, nslot = 0;
+};
+
 struct lsq_ctx {
   // problem (borrowed)
   int32_t fmt = 0, dtype = 0;
@@ -127,11 +135,14 @@ struct lsq_ctx {
   float *Mf = nullptr;    // float32 values (FP32_REFINE)
   int32_t *Mrp = nullptr, *Mci = nullptr, *Mdiag = nullptr;
 
-  // level-ordered batches of the two triangular solves
-  int G = 64;  // lanes per row in the triangular solves
-  int32_t *ord_f = nullptr, *ord_b = nullptr;
-  int4 *task_f = nullptr, *task_b = nullptr;  // CSR: (row, k0, k1, diag) per slot
-  int64_t nbatch_f = 0, nbatch_b = 0, nlev_f = 0, nlev_b = 0;
+  // triangular solves: main-block task slots (row, near range, late count)
+  // and (rows of lower levels, far slots), helper far-chunk tasks, and the
+  // triangle's entries copied in task order (values in the solve's precision)
+  int G = 64;  // lanes per row in the strict-part products
+  TriDev tri_f, tri_b;
+  void *tdg = nullptr;     // diagonal of M
+  void *farbuf = nullptr;  // far-sum slots
+  int64_t nlev_f = 0, nlev_b = 0;
 
   // float32 copy of A when A is stored in float64 (FP32_REFINE)
   const float *A32 = nullptr;
@@ -264,3 +275,4 @@ enum { KC_TRSV = 0, KC_SGS_RHS = 1, KC_ATAP = 2, KC_VEC = 3 };
 
 int lsq_hip_fail(lsq_ctx *ctx, hipError_t e, const char *what);
 void *lsq_alloc(lsq_ctx *ctx, size_t bytes);
+void lsq_free_one(lsq_ctx *ctx, void *p);

@@ -6,13 +6,23 @@
 //
 // Triangular solves keep the paper's natural row order. Rows are grouped into
 // level sets (a row's level is one more than the largest level of the rows it
-// depends on) and a single workgroup of 16 waves walks the level-ordered rows:
-// wave w takes batches w, w+16, ..., each batch a few rows of one level, and a
-// row waits only for the entries of x it reads, which are published in LDS
-// (or global memory for large n) by overwriting a NaN sentinel. A batch's
-// dependencies all lie in strictly lower levels, i.e. in earlier batches, so
-// the walk always makes progress without workgroup barriers.
+// reads). The entries of a row at level l are split by the level of the row
+// they read:
+//   late  - level l-1: the dependency chain itself;
+//   near  - levels l-D .. l-2 (D = kNearLevels);
+//   far   - levels <= l-D-1: most of the entries.
+// One workgroup (the "main" block, x in LDS) walks the rows level by level
+// and computes x_i = (r_i - far_i - near_i - late_i) / M_ii. The far sums are
+// computed ahead of time by helper workgroups on other CUs, which can start on
+// a row as soon as the rows it reads at level <= l-D-1 are known, i.e. about D
+// levels before the main block reaches it. The main block moves every x_i to
+// global memory; helpers and the main block exchange x_i and far sums through
+// slots that hold a NaN sentinel until written, so no fence or counter is
+// shared between CUs. Within the main block an LDS counter of finished rows
+// orders the levels.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -32,157 +42,330 @@ struct Bits<float> {
   static constexpr U kSent = 0x7FA0BEEFu;
 };
 
-template <typename T>
-__device__ __forceinline__ T from_bits(typename Bits<T>::U u) {
-  return __builtin_bit_cast(T, u);
-}
-template <typename T>
-__device__ __forceinline__ typename Bits<T>::U to_bits(T v) {
-  return __builtin_bit_cast(typename Bits<T>::U, v);
-}
-
 constexpr int kTrsvThreads = 1024, kTrsvWaves = kTrsvThreads / kWave;
-constexpr int kSpinLimit = 1 << 24;
+constexpr int kMainG = 16, kMainR = kWave / kMainG, kMainE = 4;  // main block: 16 lanes per row
+constexpr int kFarE = 8, kFarChunk = kWave * kFarE;               // helpers: one wave per chunk
+constexpr int kNearLevels = 32;
+constexpr int kMaxHelpers = 32;
+constexpr int kSpinLimit = 1 << 22;
 
-// One row of a solve: the row, its entry range [k0, k1) in the triangle being
-// solved (CSR positions, or positions in the dense row-major M) and the
-// position of its diagonal.
-struct RowTask {
-  int row;
-  int64_t k0, k1, dpos;
+// Bounded waiting: a wait that exceeds kSpinLimit polls raises *err, and every
+// wait gives up once *err is raised anywhere, so a failure ends all blocks.
+__device__ __forceinline__ bool give_up(int &spins, int32_t *err) {
+  ++spins;
+  if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+  if (spins > kSpinLimit) {
+    atomicOr(err, 1);
+    return true;
+  }
+  return false;
+}
+
+template <typename T>
+__device__ __forceinline__ typename Bits<T>::U ld_sync(const T *p) {
+  return __hip_atomic_load((const typename Bits<T>::U *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_sync(T *p, T v) {
+  __hip_atomic_store((typename Bits<T>::U *)p, __builtin_bit_cast(typename Bits<T>::U, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Main-block task slots (level order; a batch of kMainR slots holds rows of one
+// level, padded with row -1):
+//   a = (row, k0, k1, nl): near entries [k0, k1), late entries [k1, k1 + nl)
+//   b = (need, needE, f0, nf): rows of levels < l, rows of levels < l-1, far
+//       slots [f0, f0 + nf)
+// Helper tasks (level order of their rows): (k0, k1, slot, probe): far
+// entries [k0, k1) summed into far slot `slot`; `probe` is a column of the
+// chunk at the highest level, polled before the chunk is gathered.
+struct MainTask {
+  int4 a, b;
+  bool ok;  // false past the last batch
 };
 
-template <bool DENSE, bool UPPER, int R>
-__device__ __forceinline__ RowTask get_task(int b, int g, int nbatch, int n, const int4 *__restrict__ task,
-                                            const int32_t *__restrict__ ord) {
-  RowTask t{-1, 0, 0, 0};
-  if (b >= nbatch) return t;
-  if (DENSE) {
-    const int row = ord[b * R + g];
-    t.row = row;
-    if (row >= 0) {
-      const int64_t base = (int64_t)row * n;
-      t.dpos = base + row;
-      t.k0 = UPPER ? t.dpos + 1 : base;
-      t.k1 = UPPER ? base + n : t.dpos;
-    }
-  } else {
-    const int4 q = task[b * R + g];
-    t.row = q.x;
-    t.k0 = q.y;
-    t.k1 = q.z;
-    t.dpos = q.w;
-  }
+template <int R>
+__device__ __forceinline__ MainTask main_task(int bt, int g, int nbatch, const int4 *__restrict__ ta,
+                                              const int4 *__restrict__ tb) {
+  MainTask t;
+  t.ok = bt < nbatch;
+  const int s = t.ok ? bt * R + g : g;
+  t.a = ta[s];
+  t.b = tb[s];
   return t;
 }
 
-// E entries per lane are loaded into registers in one burst (G*E per row per
-// chunk); the next batch's row is loaded while the current row waits for its
-// dependencies, so the global-memory latency overlaps the dependency chain.
-template <typename T, bool DENSE, bool UPPER, bool LDSX, int G, int E>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__restrict__ task,
-                                                       const int32_t *__restrict__ ord,
-                                                       const int32_t *__restrict__ ci, const T *__restrict__ val,
-                                                       const T *__restrict__ rhs, T *__restrict__ x, int nbatch,
-                                                       int32_t *__restrict__ err) {
+template <typename T, bool LDSX>
+__device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
+                                          int nbatch, const int32_t *__restrict__ mci, const T *__restrict__ mval,
+                                          const T *__restrict__ diag, const T *__restrict__ rhs, T *__restrict__ x,
+                                          T *__restrict__ far, int32_t *__restrict__ err,
+                                          unsigned long long *__restrict__ trace) {
   typedef typename Bits<T>::U U;
-  constexpr int R = kWave / G;
-  constexpr int scope = LDSX ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+  constexpr int G = kMainG, R = kMainR, E = kMainE;
   extern __shared__ __align__(16) unsigned char smem[];
-  U *xs = LDSX ? (U *)smem : (U *)x;
-  for (int i = threadIdx.x; i < n; i += kTrsvThreads) __hip_atomic_store(&xs[i], Bits<T>::kSent, __ATOMIC_RELAXED, scope);
+  __shared__ int done;
+  T *xs = LDSX ? (T *)smem : x;
+  if (threadIdx.x == 0) done = 0;
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int g = lane / G, gl = lane % G;
-  bool failed = false;
+  __builtin_amdgcn_s_setprio(2);
 
-  auto load = [&](const RowTask &t, int64_t kb, int (&jj)[E], T (&vv)[E]) {
-    const int64_t base = DENSE && t.row >= 0 ? (int64_t)t.row * n : 0;
+  // x_j is read only after its level is complete; masked-off lanes read slot
+  // 0 and their products are discarded by selects
+  auto xread = [&](int j) -> T {
+    if (LDSX) return xs[j];
+    return __builtin_bit_cast(T, ld_sync(xs + j));
+  };
+  struct Buf {
+    int j[E];
+    T v[E];
+    int lj;
+    T lv;
+    U fv;
+    T dg, rv;
+    int mask, row, nl, nf, f0, need, needE;
+  };
+  // Prefetched values are not inspected before the consume stage (a read of a
+  // register whose load is in flight waits for it).
+  auto load = [&](const MainTask &t, Buf &d) {
+    const int row = t.ok ? t.a.x : -1;
+    const int k0 = t.a.y, k1 = t.a.z;
+    int mask = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t k = kb + gl + (int64_t)G * e;
-      if (t.row >= 0 && k < t.k1) {
-        jj[e] = DENSE ? (int)(k - base) : ci[k];
-        vv[e] = val[k];
-      } else {
-        jj[e] = -1;
-        vv[e] = 0;
+      const int k = k0 + gl + G * e;
+      const bool ok = row >= 0 && k < k1;
+      const int kk = ok ? k : 0;
+      d.j[e] = mci[kk];
+      d.v[e] = mval[kk];
+      mask |= ok ? (1 << e) : 0;
+    }
+    d.mask = mask | (row >= 0 && k1 - k0 > G * E ? (1 << E) : 0);
+    const int nl = row >= 0 ? t.a.w : 0, nf = row >= 0 ? t.b.w : 0;
+    const int lk = gl < nl ? k1 + gl : 0;
+    d.lj = mci[lk];
+    d.lv = mval[lk];
+    d.fv = ld_sync(far + (gl < nf ? t.b.z + gl : 0));
+    d.dg = diag[row >= 0 ? row : 0];
+    d.rv = rhs[row >= 0 ? row : 0];
+    d.row = row;
+    d.nl = nl;
+    d.nf = nf;
+    d.f0 = t.b.z;
+    d.need = row >= 0 ? t.b.x : 0;
+    d.needE = row >= 0 ? t.b.y : 0;
+  };
+  // Relaxed LDS atomics: the LDS performs a wave's operations in order, so
+  // x-store -> counter-add (writer) and counter-read -> x-reads (reader) keep
+  // their order without waiting for the outstanding prefetch loads.
+  auto wait_done = [&](int need) {
+    if (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= need) return;
+    __builtin_amdgcn_s_setprio(0);
+    int spins = 0;
+    while (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+      __builtin_amdgcn_s_sleep(1);
+      if (give_up(spins, err)) break;
+    }
+    __builtin_amdgcn_s_setprio(2);
+  };
+  auto far_value = [&](int slot, U u) -> T {  // a far sum, waited for if not yet written
+    int spins = 0;
+    while (u == Bits<T>::kSent) {
+      __builtin_amdgcn_s_sleep(2);
+      if (give_up(spins, err)) {
+        u = 0;
+        break;
+      }
+      u = ld_sync(far + slot);
+    }
+    return __builtin_bit_cast(T, u);
+  };
+  auto consume = [&](const Buf &d, int bt) {
+    const unsigned long long t_in = trace ? __builtin_readcyclecounter() : 0;
+    const int slot = bt * R + g;
+    wait_done(d.needE);
+    T xv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xv[e] = xread((d.mask >> e) & 1 ? d.j[e] : 0);
+    T acc = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T pr = d.v[e] * xv[e];
+      acc += (d.mask >> e) & 1 ? pr : (T)0;
+    }
+    if (d.mask >> E) {  // more than G*E near entries (rare): the rest from memory
+      const int4 a = ta[slot];
+      for (int k = a.y + G * E + gl; k < a.z; k += G) acc += mval[k] * xread(mci[k]);
+    }
+    // far sums, normally written long before
+    if (gl < d.nf) acc += far_value(d.f0 + gl, d.fv);
+    for (int q = G + gl; q < d.nf; q += G) acc += far_value(d.f0 + q, ld_sync(far + d.f0 + q));
+    // late entries: inputs complete once level l-1 is
+    wait_done(d.need);
+    const unsigned long long t_go = trace ? __builtin_readcyclecounter() : 0;
+    const bool lon = gl < d.nl;
+    const T lp = d.lv * xread(lon ? d.lj : 0);
+    acc += lon ? lp : (T)0;
+    if (d.nl > G) {  // more than G late entries (rare)
+      const int4 a = ta[slot];
+      for (int k = a.z + G + gl; k < a.z + d.nl; k += G) acc += mval[k] * xread(mci[k]);
+    }
+    acc = dpp_group_sum<G>(acc);  // every lane of the group holds the row sum
+    if (d.row >= 0 && gl == G - 1) {
+      const T xi = (d.rv - acc) / d.dg;
+      if (LDSX) xs[d.row] = xi;
+      st_sync(x + d.row, xi);
+      if (!LDSX) __builtin_amdgcn_s_waitcnt(0);  // x read from global memory: its store completes first
+      __hip_atomic_fetch_add(&done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (trace) {  // diagnostics (shader clock): start, late go, publish, need
+        trace[4 * slot] = t_in;
+        trace[4 * slot + 1] = t_go;
+        trace[4 * slot + 2] = __builtin_readcyclecounter();
+        trace[4 * slot + 3] = (unsigned long long)d.need;
       }
     }
   };
-  // all E reads are issued together; only entries still holding the sentinel
-  // are read again
-  auto consume = [&](const int (&jj)[E], const T (&vv)[E], T acc) -> T {
-    U u[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = jj[e] >= 0 ? __hip_atomic_load(&xs[jj[e]], __ATOMIC_RELAXED, scope) : (U)0;
-    int spins = 0;  // bounded wait: a schedule error is reported, never a hang
-    bool pending = true;
-    while (pending) {
-      pending = false;
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (u[e] == Bits<T>::kSent) {
-          u[e] = __hip_atomic_load(&xs[jj[e]], __ATOMIC_RELAXED, scope);
-          pending = pending || (u[e] == Bits<T>::kSent);
-        }
-      if (pending && ++spins > kSpinLimit) {
-        failed = true;
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (u[e] == Bits<T>::kSent) u[e] = 0;
-        pending = false;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc += vv[e] * from_bits<T>(u[e]);
-    return acc;
+  auto step = [&](int bt, const Buf &dcur, const MainTask &nx, Buf &dnx, MainTask &fetch) {
+    fetch = main_task<R>(bt + 2 * kTrsvWaves, g, nbatch, ta, tb);
+    __builtin_amdgcn_sched_barrier(0);
+    load(nx, dnx);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(dcur, bt);
   };
 
-  // the task records run two rows ahead of the data, so the data loads of the
-  // next row never wait for their own task record
-  int b = wave;
-  RowTask cur = get_task<DENSE, UPPER, R>(b, g, nbatch, n, task, ord);
-  RowTask nx = get_task<DENSE, UPPER, R>(b + kTrsvWaves, g, nbatch, n, task, ord);
-  int cj[E];
-  T cv[E];
-  load(cur, cur.k0, cj, cv);
-  T crhs = cur.row >= 0 ? rhs[cur.row] : (T)0, cdg = cur.row >= 0 ? val[cur.dpos] : (T)1;
-  for (; b < nbatch; b += kTrsvWaves) {
-    const RowTask nx2 = get_task<DENSE, UPPER, R>(b + 2 * kTrsvWaves, g, nbatch, n, task, ord);
-    // prefetch the wave's next row
-    int nj[E];
-    T nv[E];
-    load(nx, nx.k0, nj, nv);
-    const T nrhs = nx.row >= 0 ? rhs[nx.row] : (T)0, ndg = nx.row >= 0 ? val[nx.dpos] : (T)1;
+  MainTask T0, T1 = main_task<R>(wave + kTrsvWaves, g, nbatch, ta, tb), T2;
+  Buf D0, D1, D2;
+  {
+    const MainTask r0 = main_task<R>(wave, g, nbatch, ta, tb);
+    load(r0, D0);
+  }
+  // a fixed trip count with no early exit keeps the loop body straight-line
+  // for the compiler's wait-count analysis; steps past the last batch see
+  // empty tasks
+  const int trips = (nbatch - wave + 3 * kTrsvWaves - 1) / (3 * kTrsvWaves);
+  for (int it = 0, bt = wave; it < trips; ++it, bt += 3 * kTrsvWaves) {
+    step(bt, D0, T1, D1, T2);
+    step(bt + kTrsvWaves, D1, T2, D2, T0);
+    step(bt + 2 * kTrsvWaves, D2, T0, D0, T1);
+  }
+}
 
-    T acc = consume(cj, cv, (T)0);
-    for (int64_t kb = cur.k0 + (int64_t)G * E; kb < cur.k1; kb += (int64_t)G * E) {  // long rows
-      int tj[E];
-      T tv[E];
-      load(cur, kb, tj, tv);
-      acc = consume(tj, tv, acc);
-    }
-    acc = dpp_group_sum<G>(acc);
-    if (cur.row >= 0 && gl == dpp_sum_lane<G>()) {
-      const T xi = (crhs - acc) / cdg;
-      __hip_atomic_store(&xs[cur.row], to_bits<T>(xi), __ATOMIC_RELAXED, scope);
-    }
-    cur = nx;
-    nx = nx2;
+// Helper waves: far-chunk q is taken by helper wave q mod HW, in level order.
+template <typename T>
+__device__ __forceinline__ void trsv_helper(int nft, const int4 *__restrict__ ft, const int32_t *__restrict__ fci,
+                                            const T *__restrict__ fval, const T *__restrict__ x, T *__restrict__ far,
+                                            int32_t *__restrict__ err) {
+  typedef typename Bits<T>::U U;
+  constexpr int E = kFarE;
+  const int lane = threadIdx.x % kWave;
+  const int hw = (blockIdx.x - 1) * kTrsvWaves + threadIdx.x / kWave;
+  const int HW = (gridDim.x - 1) * kTrsvWaves;
+  struct Rec {
+    int4 r;
+    bool ok;
+  };
+  struct Buf {
+    int j[E];
+    T v[E];
+    int mask, slot, probe;
+  };
+  auto fetch = [&](int q) -> Rec {
+    Rec t;
+    t.ok = q < nft;
+    t.r = ft[t.ok ? q : 0];
+    return t;
+  };
+  auto load = [&](const Rec &t, Buf &d) {
+    int mask = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      cj[e] = nj[e];
-      cv[e] = nv[e];
+      const int k = t.r.x + lane + kWave * e;
+      const bool ok = t.ok && k < t.r.y;
+      const int kk = ok ? k : 0;
+      d.j[e] = fci[kk];
+      d.v[e] = fval[kk];
+      mask |= ok ? (1 << e) : 0;
     }
-    crhs = nrhs;
-    cdg = ndg;
+    d.mask = mask;
+    d.slot = t.ok ? t.r.z : -1;
+    d.probe = t.r.w;
+  };
+  auto consume = [&](const Buf &d) {
+    if (d.slot < 0) return;
+    // the probe is a column at the chunk's highest level: once it is written,
+    // the rest normally is too
+    int spins = 0;
+    while (ld_sync(x + d.probe) == Bits<T>::kSent) {
+      __builtin_amdgcn_s_sleep(4);
+      if (give_up(spins, err)) break;
+    }
+    T acc = 0;
+    int pending = d.mask;
+    for (;;) {  // all lanes take part until every lane's entries are in
+      U xv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) xv[e] = ld_sync(x + ((pending >> e) & 1 ? d.j[e] : 0));
+      int left = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool on = (pending >> e) & 1;
+        const bool ready = xv[e] != Bits<T>::kSent;
+        const T pr = d.v[e] * __builtin_bit_cast(T, xv[e]);
+        acc += on && ready ? pr : (T)0;
+        left |= on && !ready ? (1 << e) : 0;
+      }
+      pending = left;
+      if (__ballot(pending != 0) == 0) break;
+      if (give_up(spins, err)) break;
+      __builtin_amdgcn_s_sleep(4);
+    }
+    acc = dpp_group_sum<kWave>(acc);
+    if (lane == kWave - 1) st_sync(far + d.slot, acc);
+  };
+  auto step = [&](int q, const Buf &dcur, const Rec &nx, Buf &dnx, Rec &nxt) {
+    nxt = fetch(q + 2 * HW);
+    __builtin_amdgcn_sched_barrier(0);
+    load(nx, dnx);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(dcur);
+  };
+  Rec R0, R1 = fetch(hw + HW), R2;
+  Buf D0, D1, D2;
+  load(fetch(hw), D0);
+  const int trips = (nft - hw + 3 * HW - 1) / (3 * HW);
+  for (int it = 0, q = hw; it < trips; ++it, q += 3 * HW) {
+    step(q, D0, R1, D1, R2);
+    step(q + HW, D1, R2, D2, R0);
+    step(q + 2 * HW, D2, R0, D0, R1);
   }
-  if (failed) atomicOr(err, 1);
-  if (LDSX) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = from_bits<T>(xs[i]);
-  }
+}
+
+// Block 0 is the main block, blocks 1.. are helpers. All blocks must be
+// resident at once (the grid is at most 1 + kMaxHelpers one-per-CU blocks);
+// every wait is bounded and reports through err.
+template <typename T, bool LDSX>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
+                                                       int nbatch, const int32_t *__restrict__ mci,
+                                                       const T *__restrict__ mval, const T *__restrict__ diag,
+                                                       const T *__restrict__ rhs, int nft, const int4 *__restrict__ ft,
+                                                       const int32_t *__restrict__ fci, const T *__restrict__ fval,
+                                                       T *__restrict__ x, T *__restrict__ far, int32_t *__restrict__ err,
+                                                       unsigned long long *__restrict__ trace) {
+  if (blockIdx.x == 0)
+    trsv_main<T, LDSX>(n, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
+  else
+    trsv_helper<T>(nft, ft, fci, fval, x, far, err);
+}
+
+// every x and far slot starts as the sentinel
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_reset(int n, T *__restrict__ x, int nslot, T *__restrict__ far) {
+  typedef typename Bits<T>::U U;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ((U *)x)[i] = Bits<T>::kSent;
+  if (i < nslot) ((U *)far)[i] = Bits<T>::kSent;
 }
 
 // out_i = r_i - sum over the strict upper (UPPER_PART) or strict lower part of
@@ -220,93 +403,202 @@ __global__ __launch_bounds__(256) void k_sgs_rhs(int n, const int32_t *__restric
 
 // ---------------------------------------------------------------------------
 // level analysis (host): natural order, forward on the lower part, backward on
-// the upper part; rows sorted by level, each level padded to whole batches
+// the upper part; tasks in level order and the triangle entries copied in
+// task order
+
+// tci[k] = column of value position perm[k] (sparse: ci[perm[k]], dense:
+// perm[k] mod n); tv[k] = val[perm[k]]
+template <typename T>
+__global__ __launch_bounds__(256) void k_tri_gather(int64_t len, const int32_t *__restrict__ perm,
+                                                    const T *__restrict__ val, const int32_t *__restrict__ ci, int n,
+                                                    int32_t *__restrict__ tci, T *__restrict__ tv) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len; k += stride) {
+    const int32_t q = perm[k];
+    tv[k] = val[q];
+    if (tci) tci[k] = ci ? ci[q] : q % n;
+  }
+}
 
 int build_levels(lsq_ctx *ctx) {
   const int64_t n = ctx->n;
+  const bool f32 = ctx->opt.mode == LSQ_MODE_FP32_REFINE;
   std::vector<int32_t> lev_f(n, 0), lev_b(n, 0);
-  std::vector<int32_t> rp_h, dg_h;
+  std::vector<int32_t> rp_h, dg_h, ci_h;
   if (ctx->Mdense) {
+    if (n > 46340) {
+      ctx->err = "dense M larger than 46340 x 46340 is not supported";
+      return LSQ_EINVAL;
+    }
     for (int64_t i = 0; i < n; ++i) {
       lev_f[i] = (int32_t)i;
       lev_b[i] = (int32_t)(n - 1 - i);
     }
+    rp_h.resize(n + 1);
+    dg_h.resize(n);
+    for (int64_t i = 0; i <= n; ++i) rp_h[i] = (int32_t)(i * n);
+    for (int64_t i = 0; i < n; ++i) dg_h[i] = (int32_t)(i * n + i);
     ctx->G = 64;
   } else {
-    std::vector<int32_t> &rp = rp_h, &dg = dg_h;
-    rp.resize(n + 1);
-    dg.resize(n);
-    std::vector<int32_t> ci(ctx->nnzM);
-    LSQ_HIP_CHECK(hipMemcpyAsync(rp.data(), ctx->Mrp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    LSQ_HIP_CHECK(hipMemcpyAsync(ci.data(), ctx->Mci, ctx->nnzM * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    LSQ_HIP_CHECK(hipMemcpyAsync(dg.data(), ctx->Mdiag, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    rp_h.resize(n + 1);
+    dg_h.resize(n);
+    ci_h.resize(ctx->nnzM);
+    LSQ_HIP_CHECK(hipMemcpyAsync(rp_h.data(), ctx->Mrp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    LSQ_HIP_CHECK(hipMemcpyAsync(ci_h.data(), ctx->Mci, ctx->nnzM * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    LSQ_HIP_CHECK(hipMemcpyAsync(dg_h.data(), ctx->Mdiag, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
     for (int64_t i = 0; i < n; ++i) {
       int32_t lv = 0;
-      for (int32_t k = rp[i]; k < dg[i]; ++k) lv = std::max(lv, lev_f[ci[k]] + 1);
+      for (int32_t k = rp_h[i]; k < dg_h[i]; ++k) lv = std::max(lv, lev_f[ci_h[k]] + 1);
       lev_f[i] = lv;
     }
     for (int64_t i = n - 1; i >= 0; --i) {
       int32_t lv = 0;
-      for (int32_t k = dg[i] + 1; k < rp[i + 1]; ++k) lv = std::max(lv, lev_b[ci[k]] + 1);
+      for (int32_t k = dg_h[i] + 1; k < rp_h[i + 1]; ++k) lv = std::max(lv, lev_b[ci_h[k]] + 1);
       lev_b[i] = lv;
     }
-    double avg = (double)(ctx->nnzM - n) / (2.0 * (double)n);
+    const double avg = (double)(ctx->nnzM - n) / (2.0 * (double)n);
     int G = 4;
     while (G < 64 && G < avg) G <<= 1;
-    ctx->G = G;
+    ctx->G = G;  // lanes per row of the strict-part products
   }
-  const int R = 64 / ctx->G;
-  auto order = [&](const std::vector<int32_t> &lev, bool reverse, int64_t *nlev, int64_t *nbatch,
-                   std::vector<int32_t> &ord) {
+  const bool dense = ctx->Mdense;
+  constexpr int R = kMainR;
+  bool too_big = false;
+  struct Tri {
+    std::vector<int4> ta, tb, ft;
+    std::vector<int32_t> mperm, fperm;
+    int64_t nlev = 0, nbatch = 0, nslot = 0;
+  };
+  auto build = [&](const std::vector<int32_t> &lev, bool upper, Tri &t) {
     int32_t L = 0;
     for (int64_t i = 0; i < n; ++i) L = std::max(L, lev[i] + 1);
-    std::vector<int64_t> cnt(L + 1, 0);
+    std::vector<int64_t> cnt(L + 1, 0);  // cnt[l] = rows of levels < l
     for (int64_t i = 0; i < n; ++i) cnt[lev[i] + 1]++;
-    std::vector<int64_t> bstart(L + 1, 0);  // batch offsets per level
-    for (int32_t l = 0; l < L; ++l) bstart[l + 1] = bstart[l] + (cnt[l + 1] + R - 1) / R;
-    *nlev = L;
-    *nbatch = bstart[L];
-    ord.assign((size_t)(*nbatch) * R, -1);
-    std::vector<int64_t> fill(L, 0);
-    for (int64_t q = 0; q < n; ++q) {
-      const int64_t i = reverse ? n - 1 - q : q;
-      const int32_t l = lev[i];
-      ord[bstart[l] * R + fill[l]++] = (int32_t)i;
-    }
-  };
-  std::vector<int32_t> of, ob;
-  order(lev_f, false, &ctx->nlev_f, &ctx->nbatch_f, of);
-  order(lev_b, true, &ctx->nlev_b, &ctx->nbatch_b, ob);
-  if (!ctx->Mdense) {
-    // per-row tasks in level order: row, entry range of its triangle, diagonal
-    auto tasks = [&](const std::vector<int32_t> &ord, bool upper, int4 **out) -> int {
-      std::vector<int4> t(ord.size());
-      for (size_t q = 0; q < ord.size(); ++q) {
-        const int32_t i = ord[q];
-        if (i < 0) {
-          t[q] = make_int4(-1, 0, 0, 0);
-        } else if (upper) {
-          t[q] = make_int4(i, dg_h[i] + 1, rp_h[i + 1], dg_h[i]);
-        } else {
-          t[q] = make_int4(i, rp_h[i], dg_h[i], dg_h[i]);
-        }
+    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    std::vector<int32_t> byl(n);
+    {
+      std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = upper ? n - 1 - q : q;
+        byl[fill[lev[i]]++] = (int32_t)i;
       }
-      *out = (int4 *)lsq_alloc(ctx, t.size() * sizeof(int4) + 16);
-      if (!*out) return LSQ_ENOMEM;
-      LSQ_HIP_CHECK(hipMemcpy(*out, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
-      return LSQ_OK;
-    };
-    int rc = tasks(of, false, &ctx->task_f);
-    if (rc != LSQ_OK) return rc;
-    rc = tasks(ob, true, &ctx->task_b);
-    if (rc != LSQ_OK) return rc;
+    }
+    const int64_t tri = dense ? n * (n - 1) / 2 : (ctx->nnzM - n) / 2;
+    t.mperm.clear();
+    t.fperm.clear();
+    t.fperm.reserve((size_t)tri);
+    std::vector<int32_t> late, fcol;
+    for (int32_t l = 0; l < L; ++l) {
+      const int32_t need = (int32_t)cnt[l], needE = l >= 1 ? (int32_t)cnt[l - 1] : 0;
+      for (int64_t q = cnt[l]; q < cnt[l + 1]; ++q) {
+        const int32_t i = byl[q];
+        const int32_t a = upper ? dg_h[i] + 1 : rp_h[i], b = upper ? rp_h[i + 1] : dg_h[i];
+        late.clear();
+        fcol.clear();
+        const int32_t k0 = (int32_t)t.mperm.size();
+        const int64_t f0pos = (int64_t)t.fperm.size();
+        for (int32_t k = a; k < b; ++k) {
+          const int32_t j = dense ? (int32_t)(k - rp_h[i]) : ci_h[k];
+          const int32_t dl = l - lev[j];
+          if (dl == 1) {
+            late.push_back(k);
+          } else if (dl <= kNearLevels) {
+            t.mperm.push_back(k);
+          } else {
+            t.fperm.push_back(k);
+            fcol.push_back(j);
+          }
+        }
+        const int32_t k1 = (int32_t)t.mperm.size();
+        t.mperm.insert(t.mperm.end(), late.begin(), late.end());
+        // far chunks of this row, each with the column of highest level
+        const int64_t nfar = (int64_t)t.fperm.size() - f0pos;
+        const int32_t f0 = (int32_t)t.nslot;
+        int32_t nf = 0;
+        for (int64_t c0 = 0; c0 < nfar; c0 += kFarChunk, ++nf) {
+          const int64_t c1 = std::min<int64_t>(nfar, c0 + kFarChunk);
+          int32_t probe = fcol[c0];
+          for (int64_t c = c0 + 1; c < c1; ++c)
+            if (lev[fcol[c]] > lev[probe]) probe = fcol[c];
+          t.ft.push_back(make_int4((int32_t)(f0pos + c0), (int32_t)(f0pos + c1), (int32_t)t.nslot++, probe));
+        }
+        t.ta.push_back(make_int4(i, k0, k1, (int32_t)late.size()));
+        t.tb.push_back(make_int4(need, needE, f0, nf));
+      }
+      while (t.ta.size() % R) {
+        t.ta.push_back(make_int4(-1, 0, 0, 0));
+        t.tb.push_back(make_int4(0, 0, 0, 0));
+      }
+    }
+    if ((int64_t)t.fperm.size() >= INT32_MAX || t.nslot >= INT32_MAX) too_big = true;
+    t.nlev = L;
+    t.nbatch = (int64_t)t.ta.size() / R;
+  };
+  Tri tf, tbk;
+  build(lev_f, false, tf);
+  build(lev_b, true, tbk);
+  if (too_big) {
+    ctx->err = "M is too large for the triangular-solve task encoding";
+    return LSQ_EINVAL;
   }
-  ctx->ord_f = (int32_t *)lsq_alloc(ctx, of.size() * sizeof(int32_t) + 4);
-  ctx->ord_b = (int32_t *)lsq_alloc(ctx, ob.size() * sizeof(int32_t) + 4);
-  if (!ctx->ord_f || !ctx->ord_b) return LSQ_ENOMEM;
-  LSQ_HIP_CHECK(hipMemcpyAsync(ctx->ord_f, of.data(), of.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-  LSQ_HIP_CHECK(hipMemcpyAsync(ctx->ord_b, ob.data(), ob.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+  int rc;
+  auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
+    *dst = lsq_alloc(ctx, bytes + 16);
+    if (!*dst) return LSQ_ENOMEM;
+    if (bytes) LSQ_HIP_CHECK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return LSQ_OK;
+  };
+  // entries in task order, gathered on the device from M
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const void *val = f32 ? (const void *)ctx->Mf : (const void *)ctx->Md;
+  auto gather = [&](const std::vector<int32_t> &perm, int32_t **tci, void **tv) -> int {
+    int32_t *dperm;
+    const int64_t len = (int64_t)perm.size();
+    if ((rc = upload(perm.data(), len * sizeof(int32_t), (void **)&dperm)) != LSQ_OK) return rc;
+    if (tci) {
+      *tci = (int32_t *)lsq_alloc(ctx, (len + 1) * sizeof(int32_t));
+      if (!*tci) return LSQ_ENOMEM;
+      LSQ_HIP_CHECK(hipMemsetAsync(*tci, 0, (len + 1) * sizeof(int32_t), ctx->stream));
+    }
+    *tv = lsq_alloc(ctx, (len + 1) * es);
+    if (!*tv) return LSQ_ENOMEM;
+    LSQ_HIP_CHECK(hipMemsetAsync(*tv, 0, (len + 1) * es, ctx->stream));
+    if (len) {
+      const unsigned grid = (unsigned)std::min<int64_t>((len + 255) / 256, 8192);
+      const int32_t *ci = dense ? nullptr : ctx->Mci;
+      int32_t *out_ci = tci ? *tci : nullptr;
+      if (f32)
+        k_tri_gather<float><<<grid, 256, 0, ctx->stream>>>(len, dperm, (const float *)val, ci, (int)n, out_ci,
+                                                            (float *)*tv);
+      else
+        k_tri_gather<double><<<grid, 256, 0, ctx->stream>>>(len, dperm, (const double *)val, ci, (int)n, out_ci,
+                                                             (double *)*tv);
+      LSQ_HIP_CHECK(hipGetLastError());
+    }
+    LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    lsq_free_one(ctx, dperm);
+    return LSQ_OK;
+  };
+  auto place = [&](Tri &t, TriDev &d) -> int {
+    if ((rc = upload(t.ta.data(), t.ta.size() * sizeof(int4), (void **)&d.ta)) != LSQ_OK) return rc;
+    if ((rc = upload(t.tb.data(), t.tb.size() * sizeof(int4), (void **)&d.tb)) != LSQ_OK) return rc;
+    if ((rc = upload(t.ft.data(), t.ft.size() * sizeof(int4), (void **)&d.ft)) != LSQ_OK) return rc;
+    if ((rc = gather(t.mperm, &d.mci, &d.mval)) != LSQ_OK) return rc;
+    if ((rc = gather(t.fperm, &d.fci, &d.fval)) != LSQ_OK) return rc;
+    d.nbatch = t.nbatch;
+    d.nft = (int64_t)t.ft.size();
+    d.nslot = t.nslot;
+    return LSQ_OK;
+  };
+  if ((rc = place(tf, ctx->tri_f)) != LSQ_OK) return rc;
+  if ((rc = place(tbk, ctx->tri_b)) != LSQ_OK) return rc;
+  if ((rc = gather(dg_h, nullptr, &ctx->tdg)) != LSQ_OK) return rc;
+  ctx->nlev_f = tf.nlev;
+  ctx->nlev_b = tbk.nlev;
+  const int64_t ns = std::max(tf.nslot, tbk.nslot);
+  ctx->farbuf = lsq_alloc(ctx, (ns + 1) * sizeof(double));
+  if (!ctx->farbuf) return LSQ_ENOMEM;
   LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
   return LSQ_OK;
 }
@@ -314,48 +606,61 @@ int build_levels(lsq_ctx *ctx) {
 // ---------------------------------------------------------------------------
 // launch helpers
 
+// x lives in LDS when it fits in 150 KB
 template <typename T>
 static bool lds_fits(int64_t n) {
-  return n * (int64_t)sizeof(T) <= 131072;
+  return n * (int64_t)sizeof(T) <= 150 * 1024;
 }
 
-template <typename T, bool DENSE, bool UPPER, bool LDSX, int G>
-static void launch_trsv_g(lsq_ctx *c, const T *val, const T *rhs, T *x) {
-  constexpr int E = G >= 32 ? 8 : 4;
-  auto kern = k_trsv<T, DENSE, UPPER, LDSX, G, E>;
-  size_t lds = LDSX ? (size_t)c->n * sizeof(T) : 0;
+template <typename T, bool LDSX>
+static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
+  auto kern = k_trsv<T, LDSX>;
+  const size_t lds = LDSX ? (size_t)c->n * sizeof(T) : 0;
   static bool attr_set = false;
   if (LDSX && !attr_set) {
-    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipGetLastError();
     attr_set = true;
   }
-  const int32_t *ord = UPPER ? c->ord_b : c->ord_f;
-  const int nb = (int)(UPPER ? c->nbatch_b : c->nbatch_f);
-  const int4 *task = UPPER ? c->task_b : c->task_f;
-  kern<<<1, kTrsvThreads, lds, c->stream>>>((int)c->n, task, ord, c->Mci, val, rhs, x, nb, c->flags + 3);
-}
-
-template <typename T, bool DENSE, bool UPPER, bool LDSX>
-static void launch_trsv_l(lsq_ctx *c, const T *val, const T *rhs, T *x) {
-  switch (c->G) {
-    case 4: launch_trsv_g<T, DENSE, UPPER, LDSX, 4>(c, val, rhs, x); break;
-    case 8: launch_trsv_g<T, DENSE, UPPER, LDSX, 8>(c, val, rhs, x); break;
-    case 16: launch_trsv_g<T, DENSE, UPPER, LDSX, 16>(c, val, rhs, x); break;
-    case 32: launch_trsv_g<T, DENSE, UPPER, LDSX, 32>(c, val, rhs, x); break;
-    default: launch_trsv_g<T, DENSE, UPPER, LDSX, 64>(c, val, rhs, x); break;
+  const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
+  k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
+                                                                          (T *)c->farbuf);
+  const int helpers = (int)std::min<int64_t>(kMaxHelpers, (d.nft + kTrsvWaves - 1) / kTrsvWaves);
+  // diagnostics: LSQ_TRSV_TRACE=<file> appends per-row shader-clock stamps of
+  // every triangular solve (header: n, batches, rows per batch, 0; per task
+  // slot 4 words: start, late-entry wait end, publish, rows of lower levels)
+  static const char *trace_path = getenv("LSQ_TRSV_TRACE");
+  unsigned long long *trace = nullptr;
+  const size_t slots = (size_t)d.nbatch * kMainR;
+  if (trace_path) {
+    if (hipMalloc(&trace, 4 * slots * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
+    if (trace) (void)hipMemsetAsync(trace, 0, 4 * slots * sizeof(unsigned long long), c->stream);
+  }
+  kern<<<1 + helpers, kTrsvThreads, lds, c->stream>>>((int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci,
+                                                      (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft, d.ft,
+                                                      d.fci, (const T *)d.fval, x, (T *)c->farbuf, c->flags + 3,
+                                                      trace);
+  if (trace) {
+    std::vector<unsigned long long> h(4 * slots);
+    if (hipMemcpyAsync(h.data(), trace, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream) ==
+            hipSuccess &&
+        hipStreamSynchronize(c->stream) == hipSuccess) {
+      if (FILE *f = fopen(trace_path, "ab")) {
+        long long hdr[4] = {(long long)c->n, (long long)d.nbatch, kMainR, 0};
+        fwrite(hdr, sizeof(hdr), 1, f);
+        fwrite(h.data(), sizeof(unsigned long long), h.size(), f);
+        fclose(f);
+      }
+    }
+    (void)hipFree(trace);
   }
 }
 
 template <typename T, bool UPPER>
-static void launch_trsv(lsq_ctx *c, const T *val, const T *rhs, T *x) {
-  const bool lds = lds_fits<T>(c->n);
-  if (c->Mdense) {
-    if (lds) launch_trsv_g<T, true, UPPER, true, 64>(c, val, rhs, x);
-    else launch_trsv_g<T, true, UPPER, false, 64>(c, val, rhs, x);
-  } else {
-    if (lds) launch_trsv_l<T, false, UPPER, true>(c, val, rhs, x);
-    else launch_trsv_l<T, false, UPPER, false>(c, val, rhs, x);
-  }
+static void launch_trsv(lsq_ctx *c, const T *rhs, T *x) {
+  const TriDev &d = UPPER ? c->tri_b : c->tri_f;
+  if (lds_fits<T>(c->n)) launch_trsv_x<T, true>(c, d, rhs, x);
+  else launch_trsv_x<T, false>(c, d, rhs, x);
 }
 
 template <typename T, bool UPPER_PART>
@@ -404,14 +709,14 @@ static void sgs_apply(lsq_ctx *c, const T *val, const T *r, T *z, T *tmp) {
   }
   const double tb = trsv_bytes<T>(c), rb = rhs_bytes<T>(c);
   int slot = prof_begin(c, KC_TRSV);
-  launch_trsv<T, false>(c, val, r, z);  // first forward step from e = 0
+  launch_trsv<T, false>(c, r, z);  // first forward step from e = 0
   prof_end(c, slot, tb);
   for (int k = 1; k < t; ++k) {
     slot = prof_begin(c, KC_SGS_RHS);
     launch_rhs<T, true>(c, val, r, z, tmp);
     prof_end(c, slot, rb);
     slot = prof_begin(c, KC_TRSV);
-    launch_trsv<T, false>(c, val, tmp, z);
+    launch_trsv<T, false>(c, tmp, z);
     prof_end(c, slot, tb);
   }
   for (int k = 0; k < t; ++k) {
@@ -419,7 +724,7 @@ static void sgs_apply(lsq_ctx *c, const T *val, const T *r, T *z, T *tmp) {
     launch_rhs<T, false>(c, val, r, z, tmp);
     prof_end(c, slot, rb);
     slot = prof_begin(c, KC_TRSV);
-    launch_trsv<T, true>(c, val, tmp, z);
+    launch_trsv<T, true>(c, tmp, z);
     prof_end(c, slot, tb);
   }
 }

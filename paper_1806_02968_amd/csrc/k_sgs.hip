@@ -402,204 +402,385 @@ __global__ __launch_bounds__(256) void k_sgs_rhs(int n, const int32_t *__restric
 }
 
 // ---------------------------------------------------------------------------
-// level analysis (host): natural order, forward on the lower part, backward on
-// the upper part; tasks in level order and the triangle entries copied in
-// task order
+// Level analysis and task layout. Levels are computed on the device by one
+// workgroup per triangle walking the rows in solve order; the host turns the
+// levels into the level order and batch layout (O(n)); the entries of every
+// row are then split and copied into task order on the device.
 
-// tci[k] = column of value position perm[k] (sparse: ci[perm[k]], dense:
-// perm[k] mod n); tv[k] = val[perm[k]]
-template <typename T>
-__global__ __launch_bounds__(256) void k_tri_gather(int64_t len, const int32_t *__restrict__ perm,
-                                                    const T *__restrict__ val, const int32_t *__restrict__ ci, int n,
-                                                    int32_t *__restrict__ tci, T *__restrict__ tv) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len; k += stride) {
-    const int32_t q = perm[k];
-    tv[k] = val[q];
-    if (tci) tci[k] = ci ? ci[q] : q % n;
+// max over the wave of non-negative ints; lane 63 holds the result
+__device__ __forceinline__ int dpp_wave_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0xB1, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x4E, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x141, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x140, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));
+  return v;
+}
+
+// Row range of the strict lower (forward) or strict upper (backward) part.
+__device__ __forceinline__ void tri_range(bool upper, int i, const int32_t *__restrict__ rp,
+                                          const int32_t *__restrict__ dg, int *a, int *b) {
+  *a = upper ? dg[i] + 1 : rp[i];
+  *b = upper ? rp[i + 1] : dg[i];
+}
+
+// Levels of the rows of one triangle of a CSR M (block 0: lower part in
+// natural order, block 1: upper part in reverse order). Wave w takes the
+// rows w, w+16, ... of the solve order; a row's level is one more than the
+// largest level among the rows it reads, waited for in LDS (or global memory
+// when n ints do not fit) where levels start as -1. Rows read only rows
+// earlier in the solve order, so the earliest unfinished row can always
+// finish.
+template <bool LDSL>
+__global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const int32_t *__restrict__ dg, int32_t *__restrict__ lev_f,
+                                                         int32_t *__restrict__ lev_b, int32_t *__restrict__ err) {
+  constexpr int E = 8;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const bool upper = blockIdx.x == 1;
+  int32_t *out = upper ? lev_b : lev_f;
+  int32_t *lv = LDSL ? (int32_t *)smem : out;
+  constexpr int scope = LDSL ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+  if (LDSL)
+    for (int i = threadIdx.x; i < n; i += kTrsvThreads) lv[i] = -1;
+  __syncthreads();  // the global array starts at -1 (set before the launch)
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  auto level_of = [&](int j, int &spins) -> int {  // waits for row j's level
+    int v = __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope);
+    while (v < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (give_up(spins, err)) return 0;
+      v = __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope);
+    }
+    return v;
+  };
+  for (int q = wave; q < n; q += kTrsvWaves) {
+    const int i = upper ? n - 1 - q : q;
+    int a, b;
+    tri_range(upper, i, rp, dg, &a, &b);
+    int mx = -1, spins = 0;
+    for (int k0 = a; k0 < b; k0 += kWave * E) {
+      int j[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = k0 + lane + kWave * e;
+        j[e] = k < b ? ci[k] : -1;
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (j[e] >= 0) mx = max(mx, level_of(j[e], spins));
+    }
+    mx = dpp_wave_max(mx);
+    if (lane == kWave - 1) __hip_atomic_store(lv + i, mx + 1, __ATOMIC_RELAXED, scope);
   }
+  if (LDSL) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kTrsvThreads) out[i] = lv[i];
+  }
+}
+
+// Entry classes of row i (level l) by the level of the row read: late (l-1),
+// near (l-kNearLevels .. l-2), far (older). cnt[i] = (near, late, far).
+template <bool DENSE>
+__device__ __forceinline__ void row_bounds(bool upper, int n, int i, const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ dg, int64_t *a, int64_t *b) {
+  if (DENSE) {
+    const int64_t base = (int64_t)i * n;
+    *a = upper ? base + i + 1 : base;
+    *b = upper ? base + n : base + i;
+  } else {
+    *a = upper ? dg[i] + 1 : rp[i];
+    *b = upper ? rp[i + 1] : dg[i];
+  }
+}
+
+__device__ __forceinline__ int entry_class(int dl) { return dl == 1 ? 1 : (dl <= kNearLevels ? 0 : 2); }
+
+template <bool DENSE>
+__global__ __launch_bounds__(256) void k_split_count(int n, bool upper, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
+                                                     const int32_t *__restrict__ lev, int4 *__restrict__ cnt) {
+  const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  if (i >= n) return;  // whole waves
+  int64_t a, b;
+  row_bounds<DENSE>(upper, n, i, rp, dg, &a, &b);
+  const int li = lev[i];
+  int c0 = 0, c1 = 0, c2 = 0;
+  for (int64_t k = a + lane; k < b; k += kWave) {
+    const int j = DENSE ? (int)(k - (int64_t)i * n) : ci[k];
+    const int cl = entry_class(li - lev[j]);
+    c0 += cl == 0;
+    c1 += cl == 1;
+    c2 += cl == 2;
+  }
+  c0 = wave_sum(c0);
+  c1 = wave_sum(c1);
+  c2 = wave_sum(c2);
+  if (lane == 0) cnt[i] = make_int4(c0, c1, c2, 0);
+}
+
+// Copies row i's entries in task order: near then late entries at main
+// position info[i].x, far entries at far position info[i].y, each class in
+// column order (wave-wide ballot ranks).
+template <typename T, bool DENSE>
+__global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
+                                                       const T *__restrict__ val, const int32_t *__restrict__ lev,
+                                                       const int4 *__restrict__ cnt, const int4 *__restrict__ info,
+                                                       int32_t *__restrict__ mci, T *__restrict__ mval,
+                                                       int32_t *__restrict__ fci, T *__restrict__ fval) {
+  const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  if (i >= n) return;  // whole waves
+  int64_t a, b;
+  row_bounds<DENSE>(upper, n, i, rp, dg, &a, &b);
+  const int li = lev[i];
+  const int4 in = info[i];
+  int64_t pos[3] = {in.x, (int64_t)in.x + cnt[i].x, in.y};
+  for (int64_t k0 = a; k0 < b; k0 += kWave) {
+    const int64_t k = k0 + lane;
+    const bool on = k < b;
+    const int j = on ? (DENSE ? (int)(k - (int64_t)i * n) : ci[k]) : 0;
+    const int cl = on ? entry_class(li - lev[j]) : 3;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const unsigned long long m = __ballot(cl == t);
+      if (cl == t) {
+        const int64_t dst = pos[t] + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+        if (t < 2) {
+          mci[dst] = j;
+          mval[dst] = val[k];
+        } else {
+          fci[dst] = j;
+          fval[dst] = val[k];
+        }
+      }
+      pos[t] += __popcll(m);
+    }
+  }
+}
+
+// ft[c].w = a column of far chunk c at the highest level
+__global__ __launch_bounds__(256) void k_far_probe(int nft, int4 *__restrict__ ft, const int32_t *__restrict__ fci,
+                                                   const int32_t *__restrict__ lev) {
+  const int c = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x % kWave;
+  if (c >= nft) return;  // whole waves
+  const int4 r = ft[c];
+  long long key = -1;  // level * 2^31 + column
+  for (int k = r.x + lane; k < r.y; k += kWave) {
+    const int j = fci[k];
+    const long long kk = ((long long)lev[j] << 31) | j;
+    key = kk > key ? kk : key;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const long long o = __shfl_xor(key, off);
+    key = o > key ? o : key;
+  }
+  if (lane == 0) ft[c].w = (int)(key & 0x7FFFFFFF);
+}
+
+// diagonal of M in the solve's precision
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_gather(int n, bool dense, const int32_t *__restrict__ dg,
+                                                     const T *__restrict__ val, T *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = val[dense ? (int64_t)i * n + i : dg[i]];
 }
 
 int build_levels(lsq_ctx *ctx) {
   const int64_t n = ctx->n;
   const bool f32 = ctx->opt.mode == LSQ_MODE_FP32_REFINE;
-  std::vector<int32_t> lev_f(n, 0), lev_b(n, 0);
-  std::vector<int32_t> rp_h, dg_h, ci_h;
-  if (ctx->Mdense) {
-    if (n > 46340) {
-      ctx->err = "dense M larger than 46340 x 46340 is not supported";
-      return LSQ_EINVAL;
-    }
-    for (int64_t i = 0; i < n; ++i) {
-      lev_f[i] = (int32_t)i;
-      lev_b[i] = (int32_t)(n - 1 - i);
-    }
-    rp_h.resize(n + 1);
-    dg_h.resize(n);
-    for (int64_t i = 0; i <= n; ++i) rp_h[i] = (int32_t)(i * n);
-    for (int64_t i = 0; i < n; ++i) dg_h[i] = (int32_t)(i * n + i);
-    ctx->G = 64;
-  } else {
-    rp_h.resize(n + 1);
-    dg_h.resize(n);
-    ci_h.resize(ctx->nnzM);
-    LSQ_HIP_CHECK(hipMemcpyAsync(rp_h.data(), ctx->Mrp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    LSQ_HIP_CHECK(hipMemcpyAsync(ci_h.data(), ctx->Mci, ctx->nnzM * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    LSQ_HIP_CHECK(hipMemcpyAsync(dg_h.data(), ctx->Mdiag, n * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    for (int64_t i = 0; i < n; ++i) {
-      int32_t lv = 0;
-      for (int32_t k = rp_h[i]; k < dg_h[i]; ++k) lv = std::max(lv, lev_f[ci_h[k]] + 1);
-      lev_f[i] = lv;
-    }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      int32_t lv = 0;
-      for (int32_t k = dg_h[i] + 1; k < rp_h[i + 1]; ++k) lv = std::max(lv, lev_b[ci_h[k]] + 1);
-      lev_b[i] = lv;
-    }
+  const bool dense = ctx->Mdense;
+  hipStream_t st = ctx->stream;
+  if (dense && n > 46340) {
+    ctx->err = "dense M larger than 46340 x 46340 is not supported";
+    return LSQ_EINVAL;
+  }
+  if (!dense) {
     const double avg = (double)(ctx->nnzM - n) / (2.0 * (double)n);
     int G = 4;
     while (G < 64 && G < avg) G <<= 1;
     ctx->G = G;  // lanes per row of the strict-part products
+  } else {
+    ctx->G = 64;
   }
-  const bool dense = ctx->Mdense;
+  int rc;
+  auto alloc = [&](size_t bytes, void **dst) -> int {
+    *dst = lsq_alloc(ctx, bytes + 16);
+    return *dst ? LSQ_OK : LSQ_ENOMEM;
+  };
+  // levels of both triangles
+  int32_t *dlev;
+  if ((rc = alloc(2 * n * sizeof(int32_t), (void **)&dlev)) != LSQ_OK) return rc;
+  int32_t *dlev_f = dlev, *dlev_b = dlev + n;
+  std::vector<int32_t> lev_f(n), lev_b(n);
+  if (dense) {
+    for (int64_t i = 0; i < n; ++i) {
+      lev_f[i] = (int32_t)i;
+      lev_b[i] = (int32_t)(n - 1 - i);
+    }
+    LSQ_HIP_CHECK(hipMemcpyAsync(dlev_f, lev_f.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    LSQ_HIP_CHECK(hipMemcpyAsync(dlev_b, lev_b.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  } else {
+    const bool ldsl = n * 4 <= 150 * 1024;
+    if (ldsl) {
+      static bool attr = false;
+      if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_levels<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  150 * 1024);
+        (void)hipGetLastError();
+        attr = true;
+      }
+      k_levels<true><<<2, kTrsvThreads, n * 4, st>>>((int)n, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
+                                                     ctx->flags + 3);
+    } else {
+      launch_fill_i32(dlev, 2 * n, -1, st);
+      k_levels<false><<<2, kTrsvThreads, 0, st>>>((int)n, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
+                                                  ctx->flags + 3);
+    }
+    LSQ_HIP_CHECK(hipGetLastError());
+    LSQ_HIP_CHECK(hipMemcpyAsync(lev_f.data(), dlev_f, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LSQ_HIP_CHECK(hipMemcpyAsync(lev_b.data(), dlev_b, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  }
+  // entry counts per row and class
+  int4 *dcnt;
+  if ((rc = alloc(2 * n * sizeof(int4), (void **)&dcnt)) != LSQ_OK) return rc;
+  const unsigned rows_grid = (unsigned)((n * kWave + 255) / 256);
+  for (int u = 0; u < 2; ++u) {
+    const int32_t *lv = u ? dlev_b : dlev_f;
+    if (dense)
+      k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, nullptr, nullptr, nullptr, lv, dcnt + u * n);
+    else
+      k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
+                                                      dcnt + u * n);
+  }
+  LSQ_HIP_CHECK(hipGetLastError());
+  std::vector<int4> hcnt(2 * n);
+  LSQ_HIP_CHECK(hipMemcpyAsync(hcnt.data(), dcnt, 2 * n * sizeof(int4), hipMemcpyDeviceToHost, st));
+  LSQ_HIP_CHECK(hipStreamSynchronize(st));
+  int32_t hflag = 0;
+  LSQ_HIP_CHECK(hipMemcpy(&hflag, ctx->flags + 3, sizeof(hflag), hipMemcpyDeviceToHost));
+  if (hflag) {
+    ctx->err = "level analysis wait limit exceeded";
+    return LSQ_EHIP;
+  }
   constexpr int R = kMainR;
   bool too_big = false;
-  struct Tri {
-    std::vector<int4> ta, tb, ft;
-    std::vector<int32_t> mperm, fperm;
-    int64_t nlev = 0, nbatch = 0, nslot = 0;
-  };
-  auto build = [&](const std::vector<int32_t> &lev, bool upper, Tri &t) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const void *val = f32 ? (const void *)ctx->Mf : (const void *)ctx->Md;
+  int4 *dinfo;
+  if ((rc = alloc(n * sizeof(int4), (void **)&dinfo)) != LSQ_OK) return rc;
+  std::vector<int4> info(n);
+  // per triangle: level order, batch layout, positions; then the device copy
+  auto place = [&](const std::vector<int32_t> &lev, const int32_t *dl, const int4 *cnt, const int4 *dc, bool upper,
+                   TriDev &d, int64_t *nlev) -> int {
     int32_t L = 0;
     for (int64_t i = 0; i < n; ++i) L = std::max(L, lev[i] + 1);
-    std::vector<int64_t> cnt(L + 1, 0);  // cnt[l] = rows of levels < l
-    for (int64_t i = 0; i < n; ++i) cnt[lev[i] + 1]++;
-    for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+    std::vector<int64_t> lc(L + 1, 0);  // lc[l] = rows of levels < l
+    for (int64_t i = 0; i < n; ++i) lc[lev[i] + 1]++;
+    for (int32_t l = 0; l < L; ++l) lc[l + 1] += lc[l];
     std::vector<int32_t> byl(n);
     {
-      std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+      std::vector<int64_t> fill(lc.begin(), lc.end() - 1);
       for (int64_t q = 0; q < n; ++q) {
         const int64_t i = upper ? n - 1 - q : q;
         byl[fill[lev[i]]++] = (int32_t)i;
       }
     }
-    const int64_t tri = dense ? n * (n - 1) / 2 : (ctx->nnzM - n) / 2;
-    t.mperm.clear();
-    t.fperm.clear();
-    t.fperm.reserve((size_t)tri);
-    std::vector<int32_t> late, fcol;
+    std::vector<int4> ta, tb, ft;
+    ta.reserve(n + (size_t)L * R);
+    tb.reserve(n + (size_t)L * R);
+    int64_t mpos = 0, fpos = 0, slot = 0;
     for (int32_t l = 0; l < L; ++l) {
-      const int32_t need = (int32_t)cnt[l], needE = l >= 1 ? (int32_t)cnt[l - 1] : 0;
-      for (int64_t q = cnt[l]; q < cnt[l + 1]; ++q) {
+      const int32_t need = (int32_t)lc[l], needE = l >= 1 ? (int32_t)lc[l - 1] : 0;
+      for (int64_t q = lc[l]; q < lc[l + 1]; ++q) {
         const int32_t i = byl[q];
-        const int32_t a = upper ? dg_h[i] + 1 : rp_h[i], b = upper ? rp_h[i + 1] : dg_h[i];
-        late.clear();
-        fcol.clear();
-        const int32_t k0 = (int32_t)t.mperm.size();
-        const int64_t f0pos = (int64_t)t.fperm.size();
-        for (int32_t k = a; k < b; ++k) {
-          const int32_t j = dense ? (int32_t)(k - rp_h[i]) : ci_h[k];
-          const int32_t dl = l - lev[j];
-          if (dl == 1) {
-            late.push_back(k);
-          } else if (dl <= kNearLevels) {
-            t.mperm.push_back(k);
-          } else {
-            t.fperm.push_back(k);
-            fcol.push_back(j);
-          }
+        const int4 c = cnt[i];
+        const int32_t nf = (c.z + kFarChunk - 1) / kFarChunk;
+        info[i] = make_int4((int32_t)mpos, (int32_t)fpos, 0, 0);
+        ta.push_back(make_int4(i, (int32_t)mpos, (int32_t)(mpos + c.x), c.y));
+        tb.push_back(make_int4(need, needE, (int32_t)slot, nf));
+        for (int32_t f = 0; f < nf; ++f) {
+          const int64_t f0 = fpos + (int64_t)f * kFarChunk;
+          ft.push_back(make_int4((int32_t)f0, (int32_t)std::min<int64_t>(fpos + c.z, f0 + kFarChunk),
+                                 (int32_t)(slot + f), 0));
         }
-        const int32_t k1 = (int32_t)t.mperm.size();
-        t.mperm.insert(t.mperm.end(), late.begin(), late.end());
-        // far chunks of this row, each with the column of highest level
-        const int64_t nfar = (int64_t)t.fperm.size() - f0pos;
-        const int32_t f0 = (int32_t)t.nslot;
-        int32_t nf = 0;
-        for (int64_t c0 = 0; c0 < nfar; c0 += kFarChunk, ++nf) {
-          const int64_t c1 = std::min<int64_t>(nfar, c0 + kFarChunk);
-          int32_t probe = fcol[c0];
-          for (int64_t c = c0 + 1; c < c1; ++c)
-            if (lev[fcol[c]] > lev[probe]) probe = fcol[c];
-          t.ft.push_back(make_int4((int32_t)(f0pos + c0), (int32_t)(f0pos + c1), (int32_t)t.nslot++, probe));
-        }
-        t.ta.push_back(make_int4(i, k0, k1, (int32_t)late.size()));
-        t.tb.push_back(make_int4(need, needE, f0, nf));
+        mpos += c.x + c.y;
+        fpos += c.z;
+        slot += nf;
       }
-      while (t.ta.size() % R) {
-        t.ta.push_back(make_int4(-1, 0, 0, 0));
-        t.tb.push_back(make_int4(0, 0, 0, 0));
+      while (ta.size() % R) {
+        ta.push_back(make_int4(-1, 0, 0, 0));
+        tb.push_back(make_int4(0, 0, 0, 0));
       }
     }
-    if ((int64_t)t.fperm.size() >= INT32_MAX || t.nslot >= INT32_MAX) too_big = true;
-    t.nlev = L;
-    t.nbatch = (int64_t)t.ta.size() / R;
+    if (mpos >= INT32_MAX || fpos >= INT32_MAX || slot >= INT32_MAX) {
+      too_big = true;
+      return LSQ_OK;
+    }
+    *nlev = L;
+    d.nbatch = (int64_t)ta.size() / R;
+    d.nft = (int64_t)ft.size();
+    d.nslot = slot;
+    if ((rc = alloc(ta.size() * sizeof(int4), (void **)&d.ta)) != LSQ_OK) return rc;
+    if ((rc = alloc(tb.size() * sizeof(int4), (void **)&d.tb)) != LSQ_OK) return rc;
+    if ((rc = alloc(ft.size() * sizeof(int4), (void **)&d.ft)) != LSQ_OK) return rc;
+    if ((rc = alloc((mpos + 1) * sizeof(int32_t), (void **)&d.mci)) != LSQ_OK) return rc;
+    if ((rc = alloc((mpos + 1) * es, (void **)&d.mval)) != LSQ_OK) return rc;
+    if ((rc = alloc((fpos + 1) * sizeof(int32_t), (void **)&d.fci)) != LSQ_OK) return rc;
+    if ((rc = alloc((fpos + 1) * es, (void **)&d.fval)) != LSQ_OK) return rc;
+    LSQ_HIP_CHECK(hipMemcpyAsync(d.ta, ta.data(), ta.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    LSQ_HIP_CHECK(hipMemcpyAsync(d.tb, tb.data(), tb.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    if (!ft.empty())
+      LSQ_HIP_CHECK(hipMemcpyAsync(d.ft, ft.data(), ft.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    LSQ_HIP_CHECK(hipMemcpyAsync(dinfo, info.data(), n * sizeof(int4), hipMemcpyHostToDevice, st));
+    // slot 0 of each array is read by masked-off lanes: keep it finite
+    LSQ_HIP_CHECK(hipMemsetAsync(d.mci, 0, sizeof(int32_t) + 16, st));
+    LSQ_HIP_CHECK(hipMemsetAsync(d.mval, 0, es + 16, st));
+    LSQ_HIP_CHECK(hipMemsetAsync(d.fci, 0, sizeof(int32_t) + 16, st));
+    LSQ_HIP_CHECK(hipMemsetAsync(d.fval, 0, es + 16, st));
+    const int32_t *rp = dense ? nullptr : ctx->Mrp, *ci = dense ? nullptr : ctx->Mci, *dgp = dense ? nullptr : ctx->Mdiag;
+#define LSQ_SCATTER(TT, DD)                                                                                     \
+  k_split_scatter<TT, DD><<<rows_grid, 256, 0, st>>>((int)n, upper, rp, ci, dgp, (const TT *)val, dl, dc, dinfo, \
+                                                     d.mci, (TT *)d.mval, d.fci, (TT *)d.fval)
+    if (f32) {
+      if (dense) LSQ_SCATTER(float, true);
+      else LSQ_SCATTER(float, false);
+    } else {
+      if (dense) LSQ_SCATTER(double, true);
+      else LSQ_SCATTER(double, false);
+    }
+#undef LSQ_SCATTER
+    if (d.nft)
+      k_far_probe<<<(unsigned)((d.nft * kWave + 255) / 256), 256, 0, st>>>((int)d.nft, d.ft, d.fci, dl);
+    LSQ_HIP_CHECK(hipGetLastError());
+    LSQ_HIP_CHECK(hipStreamSynchronize(st));  // info and the host vectors are reused
+    return LSQ_OK;
   };
-  Tri tf, tbk;
-  build(lev_f, false, tf);
-  build(lev_b, true, tbk);
+  if ((rc = place(lev_f, dlev_f, hcnt.data(), dcnt, false, ctx->tri_f, &ctx->nlev_f)) != LSQ_OK) return rc;
+  if ((rc = place(lev_b, dlev_b, hcnt.data() + n, dcnt + n, true, ctx->tri_b, &ctx->nlev_b)) != LSQ_OK) return rc;
   if (too_big) {
     ctx->err = "M is too large for the triangular-solve task encoding";
     return LSQ_EINVAL;
   }
-  int rc;
-  auto upload = [&](const void *src, size_t bytes, void **dst) -> int {
-    *dst = lsq_alloc(ctx, bytes + 16);
-    if (!*dst) return LSQ_ENOMEM;
-    if (bytes) LSQ_HIP_CHECK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
-    return LSQ_OK;
-  };
-  // entries in task order, gathered on the device from M
-  const size_t es = f32 ? sizeof(float) : sizeof(double);
-  const void *val = f32 ? (const void *)ctx->Mf : (const void *)ctx->Md;
-  auto gather = [&](const std::vector<int32_t> &perm, int32_t **tci, void **tv) -> int {
-    int32_t *dperm;
-    const int64_t len = (int64_t)perm.size();
-    if ((rc = upload(perm.data(), len * sizeof(int32_t), (void **)&dperm)) != LSQ_OK) return rc;
-    if (tci) {
-      *tci = (int32_t *)lsq_alloc(ctx, (len + 1) * sizeof(int32_t));
-      if (!*tci) return LSQ_ENOMEM;
-      LSQ_HIP_CHECK(hipMemsetAsync(*tci, 0, (len + 1) * sizeof(int32_t), ctx->stream));
-    }
-    *tv = lsq_alloc(ctx, (len + 1) * es);
-    if (!*tv) return LSQ_ENOMEM;
-    LSQ_HIP_CHECK(hipMemsetAsync(*tv, 0, (len + 1) * es, ctx->stream));
-    if (len) {
-      const unsigned grid = (unsigned)std::min<int64_t>((len + 255) / 256, 8192);
-      const int32_t *ci = dense ? nullptr : ctx->Mci;
-      int32_t *out_ci = tci ? *tci : nullptr;
-      if (f32)
-        k_tri_gather<float><<<grid, 256, 0, ctx->stream>>>(len, dperm, (const float *)val, ci, (int)n, out_ci,
-                                                            (float *)*tv);
-      else
-        k_tri_gather<double><<<grid, 256, 0, ctx->stream>>>(len, dperm, (const double *)val, ci, (int)n, out_ci,
-                                                             (double *)*tv);
-      LSQ_HIP_CHECK(hipGetLastError());
-    }
-    LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    lsq_free_one(ctx, dperm);
-    return LSQ_OK;
-  };
-  auto place = [&](Tri &t, TriDev &d) -> int {
-    if ((rc = upload(t.ta.data(), t.ta.size() * sizeof(int4), (void **)&d.ta)) != LSQ_OK) return rc;
-    if ((rc = upload(t.tb.data(), t.tb.size() * sizeof(int4), (void **)&d.tb)) != LSQ_OK) return rc;
-    if ((rc = upload(t.ft.data(), t.ft.size() * sizeof(int4), (void **)&d.ft)) != LSQ_OK) return rc;
-    if ((rc = gather(t.mperm, &d.mci, &d.mval)) != LSQ_OK) return rc;
-    if ((rc = gather(t.fperm, &d.fci, &d.fval)) != LSQ_OK) return rc;
-    d.nbatch = t.nbatch;
-    d.nft = (int64_t)t.ft.size();
-    d.nslot = t.nslot;
-    return LSQ_OK;
-  };
-  if ((rc = place(tf, ctx->tri_f)) != LSQ_OK) return rc;
-  if ((rc = place(tbk, ctx->tri_b)) != LSQ_OK) return rc;
-  if ((rc = gather(dg_h, nullptr, &ctx->tdg)) != LSQ_OK) return rc;
-  ctx->nlev_f = tf.nlev;
-  ctx->nlev_b = tbk.nlev;
-  const int64_t ns = std::max(tf.nslot, tbk.nslot);
-  ctx->farbuf = lsq_alloc(ctx, (ns + 1) * sizeof(double));
-  if (!ctx->farbuf) return LSQ_ENOMEM;
-  LSQ_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  if ((rc = alloc(n * es, &ctx->tdg)) != LSQ_OK) return rc;
+  if (f32)
+    k_diag_gather<float><<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, dense, ctx->Mdiag, (const float *)val,
+                                                                      (float *)ctx->tdg);
+  else
+    k_diag_gather<double><<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, dense, ctx->Mdiag, (const double *)val,
+                                                                       (double *)ctx->tdg);
+  const int64_t ns = std::max(ctx->tri_f.nslot, ctx->tri_b.nslot);
+  if ((rc = alloc((ns + 1) * sizeof(double), &ctx->farbuf)) != LSQ_OK) return rc;
+  LSQ_HIP_CHECK(hipGetLastError());
+  LSQ_HIP_CHECK(hipStreamSynchronize(st));
+  lsq_free_one(ctx, dlev);
+  lsq_free_one(ctx, dcnt);
+  lsq_free_one(ctx, dinfo);
   return LSQ_OK;
 }
 

@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--atap-algo", type=int, default=0)
+    ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
     return ap.parse_args()
 
 
@@ -71,11 +72,11 @@ def main():
     def step(profile):
         if p.fmt == "dense":
             s = Solver(dev["A"], b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=args.mode, profile=profile,
-                       atap_algo=args.atap_algo)
+                       atap_algo=args.atap_algo, near_levels=args.near_levels)
         else:
             s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
                        b=b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=args.mode, profile=profile,
-                       atap_algo=args.atap_algo)
+                       atap_algo=args.atap_algo, near_levels=args.near_levels)
         x, info = s.solve()
         ks = s.kernel_stats() if profile else None
         s.close()

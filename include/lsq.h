@@ -87,6 +87,10 @@ typedef struct {
                           partial sums in LDS                                */
   int32_t profile;     /* nonzero: time every hot-kernel launch with HIP
                           events on the context's stream (lsq_get_kernel_stats) */
+  int32_t near_levels; /* triangular solves: entries reading rows at most this
+                          many levels below their own row's level are summed on
+                          the dependency chain, older ones ahead of time on
+                          other CUs (0: 48; at most 1024)                    */
 } lsq_options;
 
 /* Fills *opt with the defaults above. */

@@ -139,6 +139,7 @@ struct lsq_ctx {
   // and (rows of lower levels, far slots), helper far-chunk tasks, and the
   // triangle's entries copied in task order (values in the solve's precision)
   int G = 64;  // lanes per row in the strict-part products
+  int trsv_e = 4;  // near entries per lane of the triangular solves' main block
   TriDev tri_f, tri_b;
   void *tdg = nullptr;     // diagonal of M
   void *farbuf = nullptr;  // far-sum slots

@@ -9,7 +9,7 @@
 // reads). The entries of a row at level l are split by the level of the row
 // they read:
 //   late  - level l-1: the dependency chain itself;
-//   near  - levels l-D .. l-2 (D = kNearLevels);
+//   near  - levels l-D .. l-2 (D: near_levels option, 48 by default);
 //   far   - levels <= l-D-1: most of the entries.
 // One workgroup (the "main" block, x in LDS) walks the rows level by level
 // and computes x_i = (r_i - far_i - near_i - late_i) / M_ii. The far sums are
@@ -43,11 +43,36 @@ struct Bits<float> {
 };
 
 constexpr int kTrsvThreads = 1024, kTrsvWaves = kTrsvThreads / kWave;
-constexpr int kMainG = 16, kMainR = kWave / kMainG, kMainE = 4;  // main block: 16 lanes per row
+#ifndef LSQ_MAIN_G
+#define LSQ_MAIN_G 16
+#endif
+constexpr int kMainG = LSQ_MAIN_G, kMainR = kWave / kMainG;  // main block: lanes per row
 constexpr int kFarE = 8, kFarChunk = kWave * kFarE;               // helpers: one wave per chunk
-constexpr int kNearLevels = 32;
+// Entries reading the previous level are summed on the dependency chain by
+// up to kLateLanes lanes per row.
+constexpr int kLateLevels = 1, kLateLanes = 4;
 constexpr int kMaxHelpers = 32;
 constexpr int kSpinLimit = 1 << 22;
+
+// wave priorities of the main block: default, while polling, on the chain
+#ifndef LSQ_PRIO_BASE
+#define LSQ_PRIO_BASE 2
+#endif
+#ifndef LSQ_PRIO_POLL
+#define LSQ_PRIO_POLL 0
+#endif
+#ifndef LSQ_PRIO_LATE
+#define LSQ_PRIO_LATE 2
+#endif
+#ifndef LSQ_POLL_SLEEP
+#define LSQ_POLL_SLEEP 0
+#endif
+#ifndef LSQ_POLL_UNROLL
+#define LSQ_POLL_UNROLL 1
+#endif
+#ifndef LSQ_WAKEUP
+#define LSQ_WAKEUP 0
+#endif
 
 // Bounded waiting: a wait that exceeds kSpinLimit polls raises *err, and every
 // wait gives up once *err is raised anywhere, so a failure ends all blocks.
@@ -74,11 +99,15 @@ __device__ __forceinline__ void st_sync(T *p, T v) {
 // Main-block task slots (level order; a batch of kMainR slots holds rows of one
 // level, padded with row -1):
 //   a = (row, k0, k1, nl): near entries [k0, k1), late entries [k1, k1 + nl)
-//   b = (need, needE, f0, nf): rows of levels < l, rows of levels < l-1, far
-//       slots [f0, f0 + nf)
+//   b = (pos, 0, f0, nf): the row's position in level order, far slots
+//       [f0, f0 + nf)
+// Chain steps (level order): (pos, rows): rows at positions [pos, pos + rows),
+// all of one level.
 // Helper tasks (level order of their rows): (k0, k1, slot, probe): far
 // entries [k0, k1) summed into far slot `slot`; `probe` is a column of the
 // chunk at the highest level, polled before the chunk is gathered.
+// Entry values are stored divided by their row's diagonal, so that
+// x_i = r_i / M_ii - sum_j (M_ij / M_ii) x_j.
 struct MainTask {
   int4 a, b;
   bool ok;  // false past the last batch
@@ -95,29 +124,39 @@ __device__ __forceinline__ MainTask main_task(int bt, int g, int nbatch, const i
   return t;
 }
 
-template <typename T, bool LDSX>
+// Per row: the near entries and far sums are added and reduced over the
+// row's 16 lanes before the row's last dependencies are ready; the late
+// entries (reading level l-1) are taken by the row's last 4 lanes, which add
+// them with a 2-step quad reduction and publish x_i: the dependency chain is
+// one LDS round trip, one product and three adds per level. Every x_j is
+// read from a slot that holds the sentinel until x_j is written and is
+// polled until it does not; rows of one level may finish in any order.
+// Batches are in level order and each wave takes its batches in order, so
+// the earliest unfinished batch only reads finished rows and can finish.
+template <typename T, bool LDSX, int E>
 __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
                                           int nbatch, const int32_t *__restrict__ mci, const T *__restrict__ mval,
                                           const T *__restrict__ diag, const T *__restrict__ rhs, T *__restrict__ x,
                                           T *__restrict__ far, int32_t *__restrict__ err,
                                           unsigned long long *__restrict__ trace) {
   typedef typename Bits<T>::U U;
-  constexpr int G = kMainG, R = kMainR, E = kMainE;
+  constexpr int G = kMainG, R = kMainR, Q = G < kLateLanes ? G : kLateLanes;
+  constexpr int scope = LDSX ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int done;
   T *xs = LDSX ? (T *)smem : x;
-  if (threadIdx.x == 0) done = 0;
-  __syncthreads();
+  // x slots hold the sentinel until written (the global copy was reset
+  // before the launch)
+  if (LDSX) {
+    for (int i = threadIdx.x; i < n; i += kTrsvThreads) ((U *)xs)[i] = Bits<T>::kSent;
+    __syncthreads();
+  }
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int g = lane / G, gl = lane % G;
-  __builtin_amdgcn_s_setprio(2);
+  const int li = G - 1 - gl;  // late lanes: li < Q (the writer, lane G-1, is li = 0)
+  __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
 
-  // x_j is read only after its level is complete; masked-off lanes read slot
-  // 0 and their products are discarded by selects
-  auto xread = [&](int j) -> T {
-    if (LDSX) return xs[j];
-    return __builtin_bit_cast(T, ld_sync(xs + j));
-  };
+  // masked-off lanes read slot 0 and their products are discarded by selects
+  auto xpoll = [&](int j) -> U { return __hip_atomic_load((U *)xs + j, __ATOMIC_RELAXED, scope); };
   struct Buf {
     int j[E];
     T v[E];
@@ -125,7 +164,7 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     T lv;
     U fv;
     T dg, rv;
-    int mask, row, nl, nf, f0, need, needE;
+    int mask, row, nl, nf, f0;
   };
   // Prefetched values are not inspected before the consume stage (a read of a
   // register whose load is in flight waits for it).
@@ -144,7 +183,7 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     }
     d.mask = mask | (row >= 0 && k1 - k0 > G * E ? (1 << E) : 0);
     const int nl = row >= 0 ? t.a.w : 0, nf = row >= 0 ? t.b.w : 0;
-    const int lk = gl < nl ? k1 + gl : 0;
+    const int lk = li < Q && li < nl ? k1 + li : 0;
     d.lj = mci[lk];
     d.lv = mval[lk];
     d.fv = ld_sync(far + (gl < nf ? t.b.z + gl : 0));
@@ -154,21 +193,6 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     d.nl = nl;
     d.nf = nf;
     d.f0 = t.b.z;
-    d.need = row >= 0 ? t.b.x : 0;
-    d.needE = row >= 0 ? t.b.y : 0;
-  };
-  // Relaxed LDS atomics: the LDS performs a wave's operations in order, so
-  // x-store -> counter-add (writer) and counter-read -> x-reads (reader) keep
-  // their order without waiting for the outstanding prefetch loads.
-  auto wait_done = [&](int need) {
-    if (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= need) return;
-    __builtin_amdgcn_s_setprio(0);
-    int spins = 0;
-    while (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
-      __builtin_amdgcn_s_sleep(1);
-      if (give_up(spins, err)) break;
-    }
-    __builtin_amdgcn_s_setprio(2);
   };
   auto far_value = [&](int slot, U u) -> T {  // a far sum, waited for if not yet written
     int spins = 0;
@@ -182,50 +206,97 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     }
     return __builtin_bit_cast(T, u);
   };
+  auto late_x = [&](int j) -> T {  // x_j, polled until written
+    U u = xpoll(j);
+    if (u == Bits<T>::kSent) {
+      __builtin_amdgcn_s_setprio(LSQ_PRIO_POLL);
+      int spins = 0;
+#if LSQ_POLL_UNROLL
+      do {
+        if (LSQ_POLL_SLEEP) __builtin_amdgcn_s_sleep(LSQ_POLL_SLEEP);
+        if (give_up(spins, err)) {
+          u = 0;
+          break;
+        }
+        u = xpoll(j);
+      } while (u == Bits<T>::kSent);
+#else
+#pragma unroll 1
+      for (;;) {
+        if (LSQ_POLL_SLEEP) __builtin_amdgcn_s_sleep(LSQ_POLL_SLEEP);
+        u = xpoll(j);
+        if (u != Bits<T>::kSent) break;
+        if (give_up(spins, err)) {
+          u = 0;
+          break;
+        }
+      }
+#endif
+      __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
+    }
+    return __builtin_bit_cast(T, u);
+  };
   auto consume = [&](const Buf &d, int bt) {
     const unsigned long long t_in = trace ? __builtin_readcyclecounter() : 0;
     const int slot = bt * R + g;
-    wait_done(d.needE);
-    T xv[E];
+    // near entries: their rows are normally written long before
+    U xu[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) xv[e] = xread((d.mask >> e) & 1 ? d.j[e] : 0);
+    for (int e = 0; e < E; ++e) xu[e] = xpoll((d.mask >> e) & 1 ? d.j[e] : 0);
+    int pend = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) pend |= (d.mask >> e) & 1 && xu[e] == Bits<T>::kSent ? (1 << e) : 0;
+    if (pend) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if ((pend >> e) & 1) xu[e] = __builtin_bit_cast(U, late_x(d.j[e]));
+    }
     T acc = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const T pr = d.v[e] * xv[e];
+      const T pr = d.v[e] * __builtin_bit_cast(T, xu[e]);
       acc += (d.mask >> e) & 1 ? pr : (T)0;
     }
     if (d.mask >> E) {  // more than G*E near entries (rare): the rest from memory
       const int4 a = ta[slot];
-      for (int k = a.y + G * E + gl; k < a.z; k += G) acc += mval[k] * xread(mci[k]);
+      for (int k = a.y + G * E + gl; k < a.z; k += G) acc += mval[k] * late_x(mci[k]);
     }
     // far sums, normally written long before
     if (gl < d.nf) acc += far_value(d.f0 + gl, d.fv);
     for (int q = G + gl; q < d.nf; q += G) acc += far_value(d.f0 + q, ld_sync(far + d.f0 + q));
-    // late entries: inputs complete once level l-1 is
-    wait_done(d.need);
+    acc = dpp_group_sum<G>(acc);  // every lane of the row holds the sum
+    T base = d.rv / d.dg - acc;
+    __asm__ volatile("" : "+v"(base));  // computed here, off the chain
+    // late entries: the dependency chain
     const unsigned long long t_go = trace ? __builtin_readcyclecounter() : 0;
-    const bool lon = gl < d.nl;
-    const T lp = d.lv * xread(lon ? d.lj : 0);
-    acc += lon ? lp : (T)0;
-    if (d.nl > G) {  // more than G late entries (rare)
+    const bool lon = li < Q && li < d.nl;
+    T lacc = 0;
+    if (lon) lacc = d.lv * late_x(d.lj);
+    const unsigned long long t_read = trace ? __builtin_readcyclecounter() : 0;
+    if (d.nl > Q) {  // more than Q late entries (rare)
       const int4 a = ta[slot];
-      for (int k = a.z + G + gl; k < a.z + d.nl; k += G) acc += mval[k] * xread(mci[k]);
+      for (int k = a.z + Q + li; li < Q && k < a.z + d.nl; k += Q) lacc += mval[k] * late_x(mci[k]);
     }
-    acc = dpp_group_sum<G>(acc);  // every lane of the group holds the row sum
+    if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_LATE);
+    const unsigned long long t_ready = trace ? __builtin_readcyclecounter() : 0;
+    lacc = dpp_group_sum<Q>(lacc);
     if (d.row >= 0 && gl == G - 1) {
-      const T xi = (d.rv - acc) / d.dg;
-      if (LDSX) xs[d.row] = xi;
+      const T xi = base - lacc;
+      if (LDSX) __hip_atomic_store((U *)xs + d.row, __builtin_bit_cast(U, xi), __ATOMIC_RELAXED, scope);
+      const unsigned long long t_pub = trace ? __builtin_readcyclecounter() : 0;
       st_sync(x + d.row, xi);
-      if (!LDSX) __builtin_amdgcn_s_waitcnt(0);  // x read from global memory: its store completes first
-      __hip_atomic_fetch_add(&done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (trace) {  // diagnostics (shader clock): start, late go, publish, need
-        trace[4 * slot] = t_in;
-        trace[4 * slot + 1] = t_go;
-        trace[4 * slot + 2] = __builtin_readcyclecounter();
-        trace[4 * slot + 3] = (unsigned long long)d.need;
+      if (LSQ_WAKEUP) __asm__ volatile("s_wakeup");
+      if (trace) {  // diagnostics (shader clock): start, late start, publish, level
+        trace[8 * slot] = t_in;
+        trace[8 * slot + 1] = t_go;
+        trace[8 * slot + 2] = t_pub;
+        trace[8 * slot + 3] = (unsigned long long)tb[slot].x;
+        trace[8 * slot + 4] = t_ready;
+        trace[8 * slot + 5] = (unsigned long long)d.row;
+        trace[8 * slot + 6] = t_read;
       }
     }
+    if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
   };
   auto step = [&](int bt, const Buf &dcur, const MainTask &nx, Buf &dnx, MainTask &fetch) {
     fetch = main_task<R>(bt + 2 * kTrsvWaves, g, nbatch, ta, tb);
@@ -345,16 +416,17 @@ __device__ __forceinline__ void trsv_helper(int nft, const int4 *__restrict__ ft
 // Block 0 is the main block, blocks 1.. are helpers. All blocks must be
 // resident at once (the grid is at most 1 + kMaxHelpers one-per-CU blocks);
 // every wait is bounded and reports through err.
-template <typename T, bool LDSX>
+template <typename T, bool LDSX, int E>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
-                                                       int nbatch, const int32_t *__restrict__ mci,
+                                                       int nbatch,
+                                                       const int32_t *__restrict__ mci,
                                                        const T *__restrict__ mval, const T *__restrict__ diag,
                                                        const T *__restrict__ rhs, int nft, const int4 *__restrict__ ft,
                                                        const int32_t *__restrict__ fci, const T *__restrict__ fval,
                                                        T *__restrict__ x, T *__restrict__ far, int32_t *__restrict__ err,
                                                        unsigned long long *__restrict__ trace) {
   if (blockIdx.x == 0)
-    trsv_main<T, LDSX>(n, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
+    trsv_main<T, LDSX, E>(n, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
   else
     trsv_helper<T>(nft, ft, fci, fval, x, far, err);
 }
@@ -482,7 +554,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, const int32_t *_
 }
 
 // Entry classes of row i (level l) by the level of the row read: late (l-1),
-// near (l-kNearLevels .. l-2), far (older). cnt[i] = (near, late, far).
+// near (l-D .. l-2), far (older). cnt[i] = (near, late, far).
 template <bool DENSE>
 __device__ __forceinline__ void row_bounds(bool upper, int n, int i, const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ dg, int64_t *a, int64_t *b) {
@@ -496,10 +568,10 @@ __device__ __forceinline__ void row_bounds(bool upper, int n, int i, const int32
   }
 }
 
-__device__ __forceinline__ int entry_class(int dl) { return dl == 1 ? 1 : (dl <= kNearLevels ? 0 : 2); }
+__device__ __forceinline__ int entry_class(int dl, int D) { return dl <= kLateLevels ? 1 : (dl <= D ? 0 : 2); }
 
 template <bool DENSE>
-__global__ __launch_bounds__(256) void k_split_count(int n, bool upper, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int D, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
                                                      const int32_t *__restrict__ lev, int4 *__restrict__ cnt) {
   const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -511,7 +583,7 @@ __global__ __launch_bounds__(256) void k_split_count(int n, bool upper, const in
   int c0 = 0, c1 = 0, c2 = 0;
   for (int64_t k = a + lane; k < b; k += kWave) {
     const int j = DENSE ? (int)(k - (int64_t)i * n) : ci[k];
-    const int cl = entry_class(li - lev[j]);
+    const int cl = entry_class(li - lev[j], D);
     c0 += cl == 0;
     c1 += cl == 1;
     c2 += cl == 2;
@@ -526,7 +598,7 @@ __global__ __launch_bounds__(256) void k_split_count(int n, bool upper, const in
 // position info[i].x, far entries at far position info[i].y, each class in
 // column order (wave-wide ballot ranks).
 template <typename T, bool DENSE>
-__global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, int D, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
                                                        const T *__restrict__ val, const int32_t *__restrict__ lev,
                                                        const int4 *__restrict__ cnt, const int4 *__restrict__ info,
@@ -538,13 +610,14 @@ __global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, const 
   int64_t a, b;
   row_bounds<DENSE>(upper, n, i, rp, dg, &a, &b);
   const int li = lev[i];
+  const T di = val[DENSE ? (int64_t)i * n + i : (int64_t)dg[i]];
   const int4 in = info[i];
   int64_t pos[3] = {in.x, (int64_t)in.x + cnt[i].x, in.y};
   for (int64_t k0 = a; k0 < b; k0 += kWave) {
     const int64_t k = k0 + lane;
     const bool on = k < b;
     const int j = on ? (DENSE ? (int)(k - (int64_t)i * n) : ci[k]) : 0;
-    const int cl = on ? entry_class(li - lev[j]) : 3;
+    const int cl = on ? entry_class(li - lev[j], D) : 3;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const unsigned long long m = __ballot(cl == t);
@@ -552,10 +625,10 @@ __global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, const 
         const int64_t dst = pos[t] + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
         if (t < 2) {
           mci[dst] = j;
-          mval[dst] = val[k];
+          mval[dst] = val[k] / di;
         } else {
           fci[dst] = j;
-          fval[dst] = val[k];
+          fval[dst] = val[k] / di;
         }
       }
       pos[t] += __popcll(m);
@@ -608,6 +681,7 @@ int build_levels(lsq_ctx *ctx) {
   } else {
     ctx->G = 64;
   }
+  const int D = ctx->opt.near_levels > 0 ? ctx->opt.near_levels : 48;
   int rc;
   auto alloc = [&](size_t bytes, void **dst) -> int {
     *dst = lsq_alloc(ctx, bytes + 16);
@@ -653,9 +727,9 @@ int build_levels(lsq_ctx *ctx) {
   for (int u = 0; u < 2; ++u) {
     const int32_t *lv = u ? dlev_b : dlev_f;
     if (dense)
-      k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, nullptr, nullptr, nullptr, lv, dcnt + u * n);
+      k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, D, nullptr, nullptr, nullptr, lv, dcnt + u * n);
     else
-      k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
+      k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, D, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
                                                       dcnt + u * n);
   }
   LSQ_HIP_CHECK(hipGetLastError());
@@ -670,6 +744,7 @@ int build_levels(lsq_ctx *ctx) {
   }
   constexpr int R = kMainR;
   bool too_big = false;
+  int32_t maxnear = 0;
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const void *val = f32 ? (const void *)ctx->Mf : (const void *)ctx->Md;
   int4 *dinfo;
@@ -696,14 +771,14 @@ int build_levels(lsq_ctx *ctx) {
     tb.reserve(n + (size_t)L * R);
     int64_t mpos = 0, fpos = 0, slot = 0;
     for (int32_t l = 0; l < L; ++l) {
-      const int32_t need = (int32_t)lc[l], needE = l >= 1 ? (int32_t)lc[l - 1] : 0;
       for (int64_t q = lc[l]; q < lc[l + 1]; ++q) {
         const int32_t i = byl[q];
         const int4 c = cnt[i];
         const int32_t nf = (c.z + kFarChunk - 1) / kFarChunk;
         info[i] = make_int4((int32_t)mpos, (int32_t)fpos, 0, 0);
         ta.push_back(make_int4(i, (int32_t)mpos, (int32_t)(mpos + c.x), c.y));
-        tb.push_back(make_int4(need, needE, (int32_t)slot, nf));
+        tb.push_back(make_int4(l, 0, (int32_t)slot, nf));
+        maxnear = std::max(maxnear, c.x);
         for (int32_t f = 0; f < nf; ++f) {
           const int64_t f0 = fpos + (int64_t)f * kFarChunk;
           ft.push_back(make_int4((int32_t)f0, (int32_t)std::min<int64_t>(fpos + c.z, f0 + kFarChunk),
@@ -745,7 +820,7 @@ int build_levels(lsq_ctx *ctx) {
     LSQ_HIP_CHECK(hipMemsetAsync(d.fval, 0, es + 16, st));
     const int32_t *rp = dense ? nullptr : ctx->Mrp, *ci = dense ? nullptr : ctx->Mci, *dgp = dense ? nullptr : ctx->Mdiag;
 #define LSQ_SCATTER(TT, DD)                                                                                     \
-  k_split_scatter<TT, DD><<<rows_grid, 256, 0, st>>>((int)n, upper, rp, ci, dgp, (const TT *)val, dl, dc, dinfo, \
+  k_split_scatter<TT, DD><<<rows_grid, 256, 0, st>>>((int)n, upper, D, rp, ci, dgp, (const TT *)val, dl, dc, dinfo, \
                                                      d.mci, (TT *)d.mval, d.fci, (TT *)d.fval)
     if (f32) {
       if (dense) LSQ_SCATTER(float, true);
@@ -767,6 +842,9 @@ int build_levels(lsq_ctx *ctx) {
     ctx->err = "M is too large for the triangular-solve task encoding";
     return LSQ_EINVAL;
   }
+  int e = 1;  // near entries held per lane
+  while (e < 8 && kMainG * e < maxnear) e *= 2;
+  ctx->trsv_e = e;
   if ((rc = alloc(n * es, &ctx->tdg)) != LSQ_OK) return rc;
   if (f32)
     k_diag_gather<float><<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, dense, ctx->Mdiag, (const float *)val,
@@ -793,9 +871,9 @@ static bool lds_fits(int64_t n) {
   return n * (int64_t)sizeof(T) <= 150 * 1024;
 }
 
-template <typename T, bool LDSX>
+template <typename T, bool LDSX, int E>
 static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
-  auto kern = k_trsv<T, LDSX>;
+  auto kern = k_trsv<T, LDSX, E>;
   const size_t lds = LDSX ? (size_t)c->n * sizeof(T) : 0;
   static bool attr_set = false;
   if (LDSX && !attr_set) {
@@ -809,20 +887,21 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
   const int helpers = (int)std::min<int64_t>(kMaxHelpers, (d.nft + kTrsvWaves - 1) / kTrsvWaves);
   // diagnostics: LSQ_TRSV_TRACE=<file> appends per-row shader-clock stamps of
   // every triangular solve (header: n, batches, rows per batch, 0; per task
-  // slot 4 words: start, late-entry wait end, publish, rows of lower levels)
+  // slot 8 words: start, late-entry start, publish, level, late entries in,
+  // row, 0, 0)
   static const char *trace_path = getenv("LSQ_TRSV_TRACE");
   unsigned long long *trace = nullptr;
   const size_t slots = (size_t)d.nbatch * kMainR;
   if (trace_path) {
-    if (hipMalloc(&trace, 4 * slots * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
-    if (trace) (void)hipMemsetAsync(trace, 0, 4 * slots * sizeof(unsigned long long), c->stream);
+    if (hipMalloc(&trace, 8 * slots * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
+    if (trace) (void)hipMemsetAsync(trace, 0, 8 * slots * sizeof(unsigned long long), c->stream);
   }
   kern<<<1 + helpers, kTrsvThreads, lds, c->stream>>>((int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci,
                                                       (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft, d.ft,
                                                       d.fci, (const T *)d.fval, x, (T *)c->farbuf, c->flags + 3,
                                                       trace);
   if (trace) {
-    std::vector<unsigned long long> h(4 * slots);
+    std::vector<unsigned long long> h(8 * slots);
     if (hipMemcpyAsync(h.data(), trace, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream) ==
             hipSuccess &&
         hipStreamSynchronize(c->stream) == hipSuccess) {
@@ -840,8 +919,13 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
 template <typename T, bool UPPER>
 static void launch_trsv(lsq_ctx *c, const T *rhs, T *x) {
   const TriDev &d = UPPER ? c->tri_b : c->tri_f;
-  if (lds_fits<T>(c->n)) launch_trsv_x<T, true>(c, d, rhs, x);
-  else launch_trsv_x<T, false>(c, d, rhs, x);
+  const bool lds = lds_fits<T>(c->n);
+  switch (c->trsv_e) {
+    case 1: lds ? launch_trsv_x<T, true, 1>(c, d, rhs, x) : launch_trsv_x<T, false, 1>(c, d, rhs, x); break;
+    case 2: lds ? launch_trsv_x<T, true, 2>(c, d, rhs, x) : launch_trsv_x<T, false, 2>(c, d, rhs, x); break;
+    case 4: lds ? launch_trsv_x<T, true, 4>(c, d, rhs, x) : launch_trsv_x<T, false, 4>(c, d, rhs, x); break;
+    default: lds ? launch_trsv_x<T, true, 8>(c, d, rhs, x) : launch_trsv_x<T, false, 8>(c, d, rhs, x); break;
+  }
 }
 
 template <typename T, bool UPPER_PART>

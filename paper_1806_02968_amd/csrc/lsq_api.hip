@@ -193,6 +193,7 @@ extern "C" void lsq_default_options(lsq_options *o) {
   o->max_outer = 30;
   o->tie_eps = 0x1.0p-44;
   o->atap_algo = 0;
+  o->near_levels = 48;
 }
 
 extern "C" const char *lsq_strerror(int code) {
@@ -426,6 +427,8 @@ extern "C" int lsq_setup(const lsq_matrix *A, const double *b, double C, int32_t
   if (!(o.tie_eps >= 0.0)) o.tie_eps = 0x1.0p-44;
   if (!(o.inner_tol > 0.0)) o.inner_tol = 1e-5;
   if (o.max_outer <= 0) o.max_outer = 30;
+  if (o.near_levels <= 0) o.near_levels = 48;
+  if (o.near_levels > 1024) return LSQ_EINVAL;
 
   lsq_ctx *ctx = new lsq_ctx();
   ctx->fmt = A->format;

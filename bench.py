@@ -28,6 +28,10 @@ WORKLOADS = {
     "gaussian": "dense Gaussian 20000x100 float64; C=4, sweeps=1, tol 1e-10, seed 0",
     "graph": "Erdos-Renyi incidence 2000000x99999 (100000 vertices, vertex 0 dropped), lognormal weights; "
              "float64; C=4, sweeps=5, tol 1e-10, seed 0",
+    "udv": "dense UDV 200000x1000 float64, U from QR of a Gaussian, V orthogonal, sigma log-spaced 1..1e-6; "
+           "C=4, sweeps=5, tol 1e-10, seed 0",
+    "semigauss": "dense semi-Gaussian 2000000x2000 float32 storage: columns 1000..1999 scaled 1e-4, 1% of rows "
+                 "scaled 1e3; C=4, sweeps=5, tol 1e-10, seed 0",
 }
 
 
@@ -37,10 +41,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="sparse", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--mode", default="both", choices=["fp64", "fp32_refine", "both"],
+                    help="both: FP64 (the reported value) and FP32 inner PCG + FP64 refinement, timed alike")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--atap-algo", type=int, default=0)
     ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
+    ap.add_argument("--max-iter", type=int, default=0, help="PCG iteration cap (0: library default, 10 n)")
     return ap.parse_args()
 
 
@@ -69,42 +75,52 @@ def main():
                    col_idx=torch.from_numpy(p.col_idx).cuda())
     torch.cuda.synchronize()
 
-    def step(profile):
+    def step(mode, profile):
         if p.fmt == "dense":
-            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=args.mode, profile=profile,
-                       atap_algo=args.atap_algo, near_levels=args.near_levels)
+            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
+                       atap_algo=args.atap_algo, near_levels=args.near_levels, max_iter=args.max_iter)
         else:
             s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
-                       b=b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=args.mode, profile=profile,
-                       atap_algo=args.atap_algo, near_levels=args.near_levels)
+                       b=b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
+                       atap_algo=args.atap_algo, near_levels=args.near_levels, max_iter=args.max_iter)
         x, info = s.solve()
         ks = s.kernel_stats() if profile else None
         s.close()
         return x, info, ks
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    infos, kstats = [], []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        x, info, ks = step(True)
-        infos.append(info)
-        kstats.append(ks)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
+    def run(mode):
+        """W untimed steps, then K timed steps bracketed by synchronizations."""
+        for w in range(args.warmup):
+            step(mode, False)
+            print("[bench] %s warm-up %d/%d done" % (mode, w + 1, args.warmup), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        infos, kstats = [], []
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for k in range(args.steps):
+            x, info, ks = step(mode, True)
+            infos.append(info)
+            kstats.append(ks)
+            print("[bench] %s step %d/%d: %d iterations" % (mode, k + 1, args.steps, info["iters"]), file=sys.stderr,
+                  flush=True)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_total = ev0.elapsed_time(ev1)
+        # per-kernel-class totals over the timed region (HIP events on the library's stream)
+        classes = {}
+        for ks in kstats:
+            for k, v in ks.items():
+                c = classes.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
+                c["launches"] += v["launches"]
+                c["ms"] += v["ms"]
+                c["bytes"] += v["bytes"]
+        return dict(ms_total=ms_total, ms_per_step=ms_total / args.steps, infos=infos, classes=classes, x=x)
 
-    # per-kernel-class totals over the timed region (HIP events on the library's stream)
-    classes = {}
-    for ks in kstats:
-        for k, v in ks.items():
-            c = classes.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
-            c["launches"] += v["launches"]
-            c["ms"] += v["ms"]
-            c["bytes"] += v["bytes"]
+    modes = ["fp64", "fp32_refine"] if args.mode == "both" else [args.mode]
+    runs = {m: run(m) for m in modes}
+    main_mode = modes[0]
+    R = runs[main_mode]
+    ms_total, ms_per_step, classes, infos, x = R["ms_total"], R["ms_per_step"], R["classes"], R["infos"], R["x"]
     kernels = {}
     for k, v in classes.items():
         if v["launches"]:
@@ -116,7 +132,7 @@ def main():
     per_launch_bytes = dv["bytes"] / dv["launches"]
     avg_s = dv["ms"] / dv["launches"] * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9
-    roofline = {"kernel": {"trsv": "k_trsv", "sgs_rhs": "k_sgs_rhs", "atap": "k_atap_csr+k_scale_inplace",
+    roofline = {"kernel": {"trsv": "k_trsv", "sgs_rhs": "k_sgs_rhs", "atap": "A^T(Ap) kernels",
                            "vec": "vector kernels"}[dom],
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -136,9 +152,9 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "dtype": "f64" if main_mode == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.config], "m": p.m, "n": p.n, "nnz": p.nnz, "mode": args.mode},
+        "config": {"workload": WORKLOADS[args.config], "m": p.m, "n": p.n, "nnz": p.nnz, "mode": main_mode},
         "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
         "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
         "iters": int(last["iters"]),
@@ -150,6 +166,15 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    for m in modes[1:]:
+        r = runs[m]
+        li = r["infos"][-1]
+        ra = r["classes"].get("atap")
+        out[m] = {"ms_per_step": r["ms_per_step"], "setup_ms": float(np.mean([i["setup_ms"] for i in r["infos"]])),
+                  "solve_ms": float(np.mean([i["solve_ms"] for i in r["infos"]])), "iters": int(li["iters"]),
+                  "outer_iters": int(li["outer_iters"]), "relres_true": float(li["relres_true"]),
+                  "atap_gbs": (ra["bytes"] / ra["ms"] * 1e-6) if ra and ra["ms"] > 0 else None,
+                  "x_rel_diff_vs_fp64": float(torch.linalg.norm(r["x"] - x) / torch.linalg.norm(x))}
 
     if not args.no_cpu_baseline:
         import oracle

@@ -83,8 +83,10 @@ typedef struct {
   int64_t max_inner;   /* FP32_REFINE: inner iteration cap per outer step (0: max_iter) */
   int32_t max_outer;   /* FP32_REFINE: refinement steps cap (30)             */
   double tie_eps;      /* CDF-boundary tie band for reporting draws (2^-44)  */
-  int32_t atap_algo;   /* sparse A^T(Ap): 0 auto, 1 global atomics, 2 workgroup
-                          partial sums in LDS                                */
+  int32_t atap_algo;   /* A^T(Ap) kernel: 0 auto; sparse A: 1 global atomics,
+                          2 workgroup partial sums in LDS; dense A: 1 one
+                          wave per row, 2 row batches staged in LDS, 3 one
+                          wave per row with 16-byte loads                     */
   int32_t profile;     /* nonzero: time every hot-kernel launch with HIP
                           events on the context's stream (lsq_get_kernel_stats) */
   int32_t near_levels; /* triangular solves: entries reading rows at most this

@@ -21,6 +21,7 @@
 namespace lsq {
 
 constexpr int kAtThreads = 256, kAtWaves = kAtThreads / kWave;
+constexpr int kDenseLdsBlocks = 512;  // two per CU
 
 template <typename TA, typename CT, int NC, bool HAS_B>
 __global__ __launch_bounds__(kAtThreads) void k_atap_dense(int64_t m, int n, int64_t ld, const TA *__restrict__ A,
@@ -90,6 +91,183 @@ __global__ __launch_bounds__(kAtThreads) void k_atap_dense(int64_t m, int n, int
     __syncthreads();
   }
   for (int j = threadIdx.x; j < n; j += kAtThreads) part[blockIdx.x * (int64_t)n + j] = red[j];
+}
+
+// Dense A, one wave per row with VEC-wide loads: lane l holds columns
+// VEC*l + 64*VEC*c + e (e < VEC), so one load instruction moves 64*VEC
+// consecutive elements (16 bytes per lane). Needs n % VEC == 0 and rows aligned
+// to VEC elements. Otherwise as k_atap_dense.
+template <typename T, int V>
+struct VecT;
+template <>
+struct VecT<float, 4> {
+  typedef float4 type;
+};
+template <>
+struct VecT<double, 2> {
+  typedef double2 type;
+};
+template <typename TA, int V>
+__device__ __forceinline__ void vload(const TA *p, TA (&out)[V]) {
+  typedef typename VecT<TA, V>::type VT;
+  const VT v = *(const VT *)p;
+  if constexpr (V == 4) {
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else {
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+}
+
+template <typename TA, typename CT, int NC, int V, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_atap_dense_vec(int64_t m, int n, int64_t ld, const TA *__restrict__ A,
+                                                               const CT *__restrict__ u, const double *__restrict__ b,
+                                                               CT *__restrict__ part, int64_t rows_per_blk) {
+  __shared__ CT red[64 * NC * V];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  CT ur[NC][V], acc[NC][V];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int j = V * lane + kWave * V * c + e;
+      ur[c][e] = j < n ? u[j] : (CT)0;
+      acc[c][e] = 0;
+    }
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  int64_t r1 = r0 + rows_per_blk;
+  if (r1 > m) r1 = m;
+  for (int64_t i = r0 + wave; i < r1; i += 2 * kAtWaves) {
+    const bool two = i + kAtWaves < r1;
+    const TA *row0 = A + i * ld;
+    const TA *row1 = A + (two ? i + kAtWaves : i) * ld;
+    TA a0[NC][V], a1[NC][V];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = V * lane + kWave * V * c;
+      if (j < n) {
+        vload<TA, V>(row0 + j, a0[c]);
+        vload<TA, V>(row1 + j, a1[c]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) a0[c][e] = a1[c][e] = 0;
+      }
+    }
+    CT d0 = 0, d1 = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        d0 += (CT)a0[c][e] * ur[c][e];
+        d1 += (CT)a1[c][e] * ur[c][e];
+      }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
+    if (HAS_B) {
+      d0 = (CT)b[i] - d0;
+      d1 = two ? (CT)b[i + kAtWaves] - d1 : (CT)0;
+    }
+    if (!two) d1 = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[c][e] += d0 * (CT)a0[c][e] + d1 * (CT)a1[c][e];
+  }
+  // combine the four waves in a fixed order
+  for (int w = 0; w < kAtWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int k = V * lane + kWave * V * c + e;
+          red[k] = (w == 0 ? (CT)0 : red[k]) + acc[c][e];
+        }
+    }
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < n; j += kAtThreads) part[blockIdx.x * (int64_t)n + j] = red[j];
+}
+
+// Dense A, LDS-staged batches: a block takes R consecutive rows at a time.
+// Phase 1: wave w streams rows w, w+4, ... of the batch from HBM (64
+// consecutive elements per load instruction), forms t_r = a_r . u, or
+// b_r - a_r . u for the residual form (u staged in LDS once), and copies the
+// row into LDS. Phase 2: thread t adds
+// sum_r t_r a_r[j] for its columns j = t, t+256, ... from LDS. A is read from
+// HBM once, the per-thread state is NC accumulators, and each block writes
+// one partial output row.
+template <typename TA, typename CT, int NC, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_atap_dense_lds(int64_t m, int n, int64_t ld, const TA *__restrict__ A,
+                                                               const CT *__restrict__ u, const double *__restrict__ b,
+                                                               CT *__restrict__ part, int64_t rows_per_blk, int R) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  CT *us = (CT *)smem;   // n
+  CT *ts = us + n;       // R
+  TA *rows = (TA *)(ts + R + (R & 1));  // R x n
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  for (int j = threadIdx.x; j < n; j += kAtThreads) us[j] = u[j];
+  CT acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0;
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  __syncthreads();
+  constexpr int NR = 4 * NC;  // elements per lane of one row (n <= 256 NC)
+  constexpr int RW = sizeof(TA) * NR <= 128 ? 2 : 1;  // rows in flight per wave
+  for (int64_t rb = r0; rb < r1; rb += R) {
+    const int nr = (int)(r1 - rb < R ? r1 - rb : R);
+    // RW rows per wave at a time, each loaded in one burst of NR loads
+    for (int r = wave; r < nr; r += RW * kAtWaves) {
+      TA a[RW][NR];
+#pragma unroll
+      for (int w = 0; w < RW; ++w) {
+        const int rr = r + w * kAtWaves < nr ? r + w * kAtWaves : r;
+        const TA *row = A + (rb + rr) * ld;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const int j = lane + kWave * c;
+          a[w][c] = j < n ? row[j] : (TA)0;
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < RW; ++w) {
+        const int rr = r + w * kAtWaves;
+        if (rr >= nr) break;  // wave-uniform
+        TA *dst = rows + (int64_t)rr * n;
+        CT d = 0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const int j = lane + kWave * c;
+          if (j < n) {
+            d += (CT)a[w][c] * us[j];
+            dst[j] = a[w][c];
+          }
+        }
+        d = wave_sum(d);
+        if (lane == 0) ts[rr] = HAS_B ? (CT)b[rb + rr] - d : d;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = threadIdx.x + kAtThreads * c;
+      if (j < n) {
+        CT sacc = 0;
+        for (int r = 0; r < nr; ++r) sacc += ts[r] * (CT)rows[(int64_t)r * n + j];
+        acc[c] += sacc;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int j = threadIdx.x + kAtThreads * c;
+    if (j < n) part[blockIdx.x * (int64_t)n + j] = acc[c];
+  }
 }
 
 // first level of the partial-row reduction: blockIdx.y sums rows
@@ -262,11 +440,64 @@ static int dense_blocks(int64_t m) {
 template <typename TA, typename CT, bool HAS_B>
 static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, CT *q, const CT *s_out) {
   const int64_t m = c->m, n = c->n;
-  const int nblk = dense_blocks(m);
-  const int64_t rpb = (m + nblk - 1) / nblk;
   CT *part = (CT *)c->part;
   hipStream_t st = c->stream;
   const int nb = (int)n;
+  const int seg = 16;
+  // 16-byte loads: VEC elements per lane per load
+  constexpr int V = 16 / sizeof(TA);
+  const bool vec_ok = n % V == 0 && c->ld % V == 0 && ((uintptr_t)A % 16) == 0 && n <= kWave * V * 8;
+  // LDS-staged batches while a batch of at least 4 rows fits in 64 KB
+  const int64_t lds_budget = 64 * 1024 - 64;
+  const int64_t R = std::min<int64_t>(64, (lds_budget - (n + 2) * (int64_t)sizeof(CT)) / (n * (int64_t)sizeof(TA)));
+  const bool lds_ok = n <= 256 * 16 && R >= 4;
+  int algo = c->opt.atap_algo;
+  if (algo == 0 || (algo == 3 && !vec_ok) || (algo == 2 && !lds_ok)) {
+    // registers hold u, the output row and two rows of A per lane; the
+    // LDS-staged form takes over when that does not fit (float storage,
+    // float64 arithmetic, long rows)
+    const int64_t per_lane = (n + kWave - 1) / kWave * (2 * sizeof(TA) + 2 * sizeof(CT)) / 4;
+    algo = per_lane <= 128 ? (vec_ok ? 3 : 1) : (lds_ok ? 2 : 1);
+  }
+  if (algo == 3) {
+    const int nblk = dense_blocks(m);
+    const int64_t rpb = (m + nblk - 1) / nblk;
+    const int nc = (int)((n + kWave * V - 1) / (kWave * V));
+    if (nc <= 1) k_atap_dense_vec<TA, CT, 1, V, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    else if (nc <= 2) k_atap_dense_vec<TA, CT, 2, V, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    else if (nc <= 4) k_atap_dense_vec<TA, CT, 4, V, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    else k_atap_dense_vec<TA, CT, 8, V, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    const int nseg = (nblk + seg - 1) / seg;
+    CT *part2 = part + (int64_t)nblk * n;
+    const int64_t fb = (n + 255) / 256;
+    k_part_reduce<CT><<<dim3((unsigned)fb, (unsigned)nseg), 256, 0, st>>>(n, part, nblk, seg, part2);
+    k_atap_finish<CT><<<(unsigned)fb, 256, 0, st>>>(n, part2, nseg, s_out, q);
+    return;
+  }
+  if (algo == 2) {
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kDenseLdsBlocks, (m + R - 1) / R));
+    const int64_t rpb = (m + nblk - 1) / nblk;
+    const size_t lds = (n + R + 2) * sizeof(CT) + R * n * sizeof(TA);
+    const int r = (int)R;
+    if (n <= 256)
+      k_atap_dense_lds<TA, CT, 1, HAS_B><<<nblk, kAtThreads, lds, st>>>(m, nb, c->ld, A, u, b, part, rpb, r);
+    else if (n <= 512)
+      k_atap_dense_lds<TA, CT, 2, HAS_B><<<nblk, kAtThreads, lds, st>>>(m, nb, c->ld, A, u, b, part, rpb, r);
+    else if (n <= 1024)
+      k_atap_dense_lds<TA, CT, 4, HAS_B><<<nblk, kAtThreads, lds, st>>>(m, nb, c->ld, A, u, b, part, rpb, r);
+    else if (n <= 2048)
+      k_atap_dense_lds<TA, CT, 8, HAS_B><<<nblk, kAtThreads, lds, st>>>(m, nb, c->ld, A, u, b, part, rpb, r);
+    else
+      k_atap_dense_lds<TA, CT, 16, HAS_B><<<nblk, kAtThreads, lds, st>>>(m, nb, c->ld, A, u, b, part, rpb, r);
+    const int nseg = (nblk + seg - 1) / seg;
+    CT *part2 = part + (int64_t)nblk * n;
+    const int64_t fb = (n + 255) / 256;
+    k_part_reduce<CT><<<dim3((unsigned)fb, (unsigned)nseg), 256, 0, st>>>(n, part, nblk, seg, part2);
+    k_atap_finish<CT><<<(unsigned)fb, 256, 0, st>>>(n, part2, nseg, s_out, q);
+    return;
+  }
+  const int nblk = dense_blocks(m);
+  const int64_t rpb = (m + nblk - 1) / nblk;
   if (n <= 64) k_atap_dense<TA, CT, 1, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
   else if (n <= 128) k_atap_dense<TA, CT, 2, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
   else if (n <= 256) k_atap_dense<TA, CT, 4, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
@@ -278,7 +509,6 @@ static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, 
     k_gemv_rows<TA, CT, HAS_B><<<8192, kAtThreads, 0, st>>>(m, n, c->ld, A, u, b, y);
     k_gemv_t_part<TA, CT><<<nblk, kAtThreads, 0, st>>>(m, n, c->ld, A, y, part, rpb);
   }
-  const int seg = 16;
   const int nseg = (nblk + seg - 1) / seg;
   CT *part2 = part + (int64_t)nblk * n;
   const int64_t fb = (n + 255) / 256;

@@ -19,6 +19,8 @@ import dataclasses
 import math
 from typing import Optional
 
+import os
+
 import numpy as np
 
 # stream ids (fixed; changing one changes the inputs of every test and bench)
@@ -82,9 +84,11 @@ class Problem:
 
 def _dense_times(A: np.ndarray, x: np.ndarray) -> np.ndarray:
     out = np.empty(A.shape[0], dtype=np.float64)
-    for r0 in range(0, A.shape[0], _CHUNK_ROWS):
-        r1 = min(A.shape[0], r0 + _CHUNK_ROWS)
+
+    def fill(c, r0, r1):
         out[r0:r1] = A[r0:r1].astype(np.float64) @ x
+
+    _chunks(A.shape[0], fill)
     return out
 
 
@@ -103,11 +107,27 @@ def _finish(p: Problem, noise: float, seed: int, with_target: bool) -> Problem:
     return p
 
 
+def _chunks(m: int, fill) -> None:
+    """Runs fill(c, r0, r1) over the row chunks of an m-row array on a few
+    threads; every chunk has its own random stream, so the result does not
+    depend on the order."""
+    jobs = [(c, r0, min(m, r0 + _CHUNK_ROWS)) for c, r0 in enumerate(range(0, m, _CHUNK_ROWS))]
+    if len(jobs) < 4:
+        for j in jobs:
+            fill(*j)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda j: fill(*j), jobs))
+
+
 def _fill_normal(m: int, n: int, seed: int, stream: int, dtype) -> np.ndarray:
     A = np.empty((m, n), dtype=dtype)
-    for c, r0 in enumerate(range(0, m, _CHUNK_ROWS)):
-        r1 = min(m, r0 + _CHUNK_ROWS)
+
+    def fill(c, r0, r1):
         A[r0:r1] = _rng(seed, stream, c).standard_normal((r1 - r0, n), dtype=np.float64).astype(dtype)
+
+    _chunks(m, fill)
     return A
 
 
@@ -262,11 +282,13 @@ def semi_gaussian_dense(m: int, n: int, seed: int = 0, noise: float = 1e-6, smal
     """
     A = np.empty((m, n), dtype=dtype)
     h = n // 2
-    for c, r0 in enumerate(range(0, m, _CHUNK_ROWS)):
-        r1 = min(m, r0 + _CHUNK_ROWS)
+
+    def fill(c, r0, r1):
         blk = _rng(seed, _S_A, c).standard_normal((r1 - r0, n))
         blk[:, h:] *= small
         A[r0:r1] = blk.astype(dtype)
+
+    _chunks(m, fill)
     nh = int(round(heavy_frac * m))
     heavy = np.sort(_rng(seed, _S_HEAVY).choice(m, size=nh, replace=False))
     for r0 in range(0, nh, 4096):

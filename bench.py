@@ -22,6 +22,12 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG solve s & Aᵀ(Ap) HBM GB/s; FP32+refine vs FP64 at 1e-10 residual"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (calibrated on a 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0), per workload and kernel class; the profile summary in profiles/
+# gives the commands. Measured on the triangular-solve code of this revision.
+MEASURED_TRAFFIC = {("sparse", "trsv"): 57.89e6}
+
 WORKLOADS = {
     "sparse": "sparse CSR 1000000x10000, 10 nnz/row at uniform distinct columns, N(0,1) values, "
               "rows scaled by 10^U(-3,3); float64; C=4, sweeps=2, tol 1e-10, seed 0",
@@ -47,6 +53,8 @@ def parse():
     ap.add_argument("--atap-algo", type=int, default=0)
     ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
     ap.add_argument("--max-iter", type=int, default=0, help="PCG iteration cap (0: library default, 10 n)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device twice (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -59,6 +67,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print("copied %d bytes twice" % (a.numel() * 4), flush=True)
+        return
 
     from paper_1806_02968_amd import Solver
     from workloads import make_config
@@ -135,7 +153,7 @@ def main():
     roofline = {"kernel": {"trsv": "k_trsv", "sgs_rhs": "k_sgs_rhs", "atap": "A^T(Ap) kernels",
                            "vec": "vector kernels"}[dom],
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.config, dom)),
                 "bytes_per_launch": per_launch_bytes, "avg_launch_us": avg_s * 1e6}
     at = classes.get("atap")
     atap_gbs = (at["bytes"] / at["ms"] * 1e-6) if at and at["ms"] > 0 else None

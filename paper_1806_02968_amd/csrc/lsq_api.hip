@@ -7,6 +7,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -20,25 +23,94 @@ int lsq_hip_fail(lsq_ctx *ctx, hipError_t e, const char *what) {
   return LSQ_EHIP;
 }
 
+// Device memory: a process-wide cache of freed blocks, keyed by device and
+// rounded size. A context's blocks return to the cache when it is destroyed
+// (after its stream has drained) or when a temporary is released (after a
+// stream synchronisation), so repeated setups reuse the same blocks instead of
+// paying hipMalloc/hipFree every time. Blocks stay allocated until the process
+// ends.
+static std::mutex g_pool_mu;
+static std::map<std::pair<int, size_t>, std::vector<void *>> g_blocks;
+
+static size_t round_size(size_t bytes) {
+  if (bytes <= (1u << 20)) {
+    size_t r = 4096;
+    while (r < bytes) r <<= 1;
+    return r;
+  }
+  return (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+}
+
 void *lsq_alloc(lsq_ctx *ctx, size_t bytes) {
+  const size_t rb = round_size(bytes < 16 ? 16 : bytes);
   void *p = nullptr;
-  if (bytes < 16) bytes = 16;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_blocks.find({ctx->device, rb});
+    if (it != g_blocks.end() && !it->second.empty()) {
+      p = it->second.back();
+      it->second.pop_back();
+    }
+  }
+  if (!p && hipMalloc(&p, rb) != hipSuccess) {
     (void)hipGetLastError();
     ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
     return nullptr;
   }
-  ctx->allocs.push_back(Dev{p, bytes});
+  ctx->allocs.push_back(Dev{p, rb});
   return p;
+}
+
+static void release_blocks(int device, const std::vector<Dev> &blocks) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (const Dev &d : blocks) g_blocks[{device, d.bytes}].push_back(d.p);
 }
 
 void lsq_free_one(lsq_ctx *ctx, void *p) {
   for (size_t i = 0; i < ctx->allocs.size(); ++i)
     if (ctx->allocs[i].p == p) {
-      (void)hipFree(p);
+      (void)hipStreamSynchronize(ctx->stream);  // no queued kernel still uses it
+      release_blocks(ctx->device, {ctx->allocs[i]});
       ctx->allocs.erase(ctx->allocs.begin() + i);
       return;
     }
+}
+
+// pinned host scalars and timing events are kept in process-wide free lists
+static std::vector<double *> g_pinned;
+static std::vector<hipEvent_t> g_events;
+
+static double *take_pinned(size_t count) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pinned.empty()) {
+      double *p = g_pinned.back();
+      g_pinned.pop_back();
+      return p;
+    }
+  }
+  double *p = nullptr;
+  if (hipHostMalloc((void **)&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+  return p;
+}
+static void give_pinned(double *p) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pinned.push_back(p);
+}
+static hipError_t take_event(hipEvent_t *e) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_events.empty()) {
+      *e = g_events.back();
+      g_events.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipEventCreate(e);
+}
+static void give_event(hipEvent_t e) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_events.push_back(e);
 }
 
 #define RET(code)                 \
@@ -111,7 +183,7 @@ int prof_begin(lsq_ctx *c, int cls) {
   if (!c->opt.profile) return -1;
   if (!c->prof_ready) {
     for (int i = 0; i < 2 * lsq_ctx::kProfSlots; ++i)
-      if (hipEventCreate(&c->prof_ev[i]) != hipSuccess) return -1;
+      if (take_event(&c->prof_ev[i]) != hipSuccess) return -1;
     c->prof_ready = true;
   }
   if (c->prof_used == lsq_ctx::kProfSlots) {
@@ -217,10 +289,11 @@ extern "C" void lsq_destroy(lsq_ctx *ctx) {
   if (!ctx) return;
   if (ctx->prof_ready) {
     (void)hipStreamSynchronize(ctx->stream);
-    for (int i = 0; i < 2 * lsq_ctx::kProfSlots; ++i) (void)hipEventDestroy(ctx->prof_ev[i]);
+    for (int i = 0; i < 2 * lsq_ctx::kProfSlots; ++i) give_event(ctx->prof_ev[i]);
   }
-  for (auto &a : ctx->allocs) (void)hipFree(a.p);
-  if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+  (void)hipStreamSynchronize(ctx->stream);  // nothing queued still uses the blocks or the pinned scalars
+  release_blocks(ctx->device, ctx->allocs);
+  if (ctx->hscal) give_pinned(ctx->hscal);
   delete ctx;
 }
 
@@ -241,7 +314,8 @@ static int setup_impl(lsq_ctx *ctx) {
 
   ALLOC(ctx->flags, int32_t, 8);
   ALLOC(ctx->scal, double, Scal::COUNT);
-  LSQ_HIP_CHECK(hipHostMalloc((void **)&ctx->hscal, Scal::COUNT * sizeof(double), hipHostMallocDefault));
+  ctx->hscal = take_pinned(Scal::COUNT);
+  if (!ctx->hscal) RET(LSQ_ENOMEM);
   ALLOC(ctx->D, double, n);
   ALLOC(ctx->invD, double, n);
   if (fp32) ALLOC(ctx->invD32, float, n);

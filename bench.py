@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG solve s & Aᵀ(Ap) HBM GB/s; FP32+refine vs FP64 at 1e-10 residual"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}  # dense matrix-core peaks, float64 / float32
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (calibrated on a 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE
@@ -140,6 +141,7 @@ def main():
     R = runs[main_mode]
     ms_total, ms_per_step, classes, infos, x = R["ms_total"], R["ms_per_step"], R["classes"], R["infos"], R["x"]
     kernels = {}
+    gram = classes.pop("gram", None)
     for k, v in classes.items():
         if v["launches"]:
             kernels[k] = dict(launches=v["launches"], avg_us=1e3 * v["ms"] / v["launches"],
@@ -184,15 +186,26 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if gram and gram["launches"]:
+        # dense Gram product on MFMA: flops / time against the dense matrix-core peak of its precision
+        peak = MFMA_PEAK_TFLOPS[main_mode]
+        tf = gram["bytes"] / (gram["ms"] * 1e-3) / 1e12
+        out["gram"] = {"launches": gram["launches"], "avg_ms": gram["ms"] / gram["launches"], "tflops": tf,
+                       "peak_tflops": peak, "frac": tf / peak}
     for m in modes[1:]:
         r = runs[m]
         li = r["infos"][-1]
         ra = r["classes"].get("atap")
+        rg = r["classes"].get("gram")
         out[m] = {"ms_per_step": r["ms_per_step"], "setup_ms": float(np.mean([i["setup_ms"] for i in r["infos"]])),
                   "solve_ms": float(np.mean([i["solve_ms"] for i in r["infos"]])), "iters": int(li["iters"]),
                   "outer_iters": int(li["outer_iters"]), "relres_true": float(li["relres_true"]),
                   "atap_gbs": (ra["bytes"] / ra["ms"] * 1e-6) if ra and ra["ms"] > 0 else None,
                   "x_rel_diff_vs_fp64": float(torch.linalg.norm(r["x"] - x) / torch.linalg.norm(x))}
+        if rg and rg["launches"]:
+            tf = rg["bytes"] / (rg["ms"] * 1e-3) / 1e12
+            out[m]["gram"] = {"avg_ms": rg["ms"] / rg["launches"], "tflops": tf,
+                              "peak_tflops": MFMA_PEAK_TFLOPS[m], "frac": tf / MFMA_PEAK_TFLOPS[m]}
 
     if not args.no_cpu_baseline:
         import oracle

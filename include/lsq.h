@@ -182,11 +182,19 @@ int lsq_apply_K(lsq_ctx *ctx, const double *p, double *q);
 
 /* Per-kernel-class launch statistics accumulated while opt.profile is set:
  * class 0 = triangular solve of Algorithm 3, 1 = its strict-part product,
- * 2 = the fused A^T(A p) pass (with its reduction), 3 = vector kernels.
+ * 2 = the fused A^T(A p) pass (with its reduction), 3 = vector kernels,
+ * 4 = the dense Gram product M = A_s^T A_s (MFMA; setup, Section 3.3).
  * bytes[] are ALGORITHMIC bytes: one read of every stored entry the kernel
- * needs (value + column index) and of its vectors, one write of its output.
+ * needs (value + column index) and of its vectors, one write of its output;
+ * for class 4 it holds floating-point operations instead (2 per
+ * multiply-add of the n(n+1)/2 distinct entries of M).
  * reset != 0 clears the counters after copying them.                       */
-#define LSQ_KCLASSES 4
+#define LSQ_KC_TRSV 0
+#define LSQ_KC_SGS_RHS 1
+#define LSQ_KC_ATAP 2
+#define LSQ_KC_VEC 3
+#define LSQ_KC_GRAM 4
+#define LSQ_KCLASSES 5
 typedef struct {
   int64_t launches[LSQ_KCLASSES];
   double ms[LSQ_KCLASSES];

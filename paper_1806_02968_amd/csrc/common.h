@@ -116,6 +116,7 @@ struct lsq_ctx {
   int32_t sweeps = 1;
   uint64_t seed = 0;
   int device = 0;
+  int ncu = 1;  // compute units of the device
 
   // setup results
   double *D = nullptr, *invD = nullptr, *w = nullptr, *cdf = nullptr;
@@ -265,7 +266,7 @@ namespace lsq {
 int prof_begin(lsq_ctx *c, int cls);
 void prof_end(lsq_ctx *c, int slot, double bytes);
 void prof_harvest(lsq_ctx *c);  // call after the stream has been synchronised
-enum { KC_TRSV = 0, KC_SGS_RHS = 1, KC_ATAP = 2, KC_VEC = 3 };
+enum { KC_TRSV = LSQ_KC_TRSV, KC_SGS_RHS = LSQ_KC_SGS_RHS, KC_ATAP = LSQ_KC_ATAP, KC_VEC = LSQ_KC_VEC, KC_GRAM = LSQ_KC_GRAM };
 }  // namespace lsq
 
 #define LSQ_HIP_CHECK(expr)                                   \

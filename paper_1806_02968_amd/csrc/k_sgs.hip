@@ -134,7 +134,7 @@ __device__ __forceinline__ MainTask main_task(int bt, int g, int nbatch, const i
 // Batches are in level order and each wave takes its batches in order, so
 // the earliest unfinished batch only reads finished rows and can finish.
 template <typename T, bool LDSX, int E>
-__device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
+__device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
                                           int nbatch, const int32_t *__restrict__ mci, const T *__restrict__ mval,
                                           const T *__restrict__ diag, const T *__restrict__ rhs, T *__restrict__ x,
                                           T *__restrict__ far, int32_t *__restrict__ err,
@@ -150,7 +150,10 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     for (int i = threadIdx.x; i < n; i += kTrsvThreads) ((U *)xs)[i] = Bits<T>::kSent;
     __syncthreads();
   }
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // with x in global memory several main blocks share the batches: wave w
+  // of all main blocks takes batches w, w + NW, ...
+  const int wave = blockIdx.x * kTrsvWaves + threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int NW = nmain * kTrsvWaves;
   const int g = lane / G, gl = lane % G;
   const int li = G - 1 - gl;  // late lanes: li < Q (the writer, lane G-1, is li = 0)
   __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
@@ -299,14 +302,14 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
     if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
   };
   auto step = [&](int bt, const Buf &dcur, const MainTask &nx, Buf &dnx, MainTask &fetch) {
-    fetch = main_task<R>(bt + 2 * kTrsvWaves, g, nbatch, ta, tb);
+    fetch = main_task<R>(bt + 2 * NW, g, nbatch, ta, tb);
     __builtin_amdgcn_sched_barrier(0);
     load(nx, dnx);
     __builtin_amdgcn_sched_barrier(0);
     consume(dcur, bt);
   };
 
-  MainTask T0, T1 = main_task<R>(wave + kTrsvWaves, g, nbatch, ta, tb), T2;
+  MainTask T0, T1 = main_task<R>(wave + NW, g, nbatch, ta, tb), T2;
   Buf D0, D1, D2;
   {
     const MainTask r0 = main_task<R>(wave, g, nbatch, ta, tb);
@@ -315,24 +318,25 @@ __device__ __forceinline__ void trsv_main(int n, const int4 *__restrict__ ta, co
   // a fixed trip count with no early exit keeps the loop body straight-line
   // for the compiler's wait-count analysis; steps past the last batch see
   // empty tasks
-  const int trips = (nbatch - wave + 3 * kTrsvWaves - 1) / (3 * kTrsvWaves);
-  for (int it = 0, bt = wave; it < trips; ++it, bt += 3 * kTrsvWaves) {
+  const int trips = (nbatch - wave + 3 * NW - 1) / (3 * NW);
+  for (int it = 0, bt = wave; it < trips; ++it, bt += 3 * NW) {
     step(bt, D0, T1, D1, T2);
-    step(bt + kTrsvWaves, D1, T2, D2, T0);
-    step(bt + 2 * kTrsvWaves, D2, T0, D0, T1);
+    step(bt + NW, D1, T2, D2, T0);
+    step(bt + 2 * NW, D2, T0, D0, T1);
   }
 }
 
 // Helper waves: far-chunk q is taken by helper wave q mod HW, in level order.
 template <typename T>
-__device__ __forceinline__ void trsv_helper(int nft, const int4 *__restrict__ ft, const int32_t *__restrict__ fci,
+__device__ __forceinline__ void trsv_helper(int nmain, int nft, const int4 *__restrict__ ft,
+                                            const int32_t *__restrict__ fci,
                                             const T *__restrict__ fval, const T *__restrict__ x, T *__restrict__ far,
                                             int32_t *__restrict__ err) {
   typedef typename Bits<T>::U U;
   constexpr int E = kFarE;
   const int lane = threadIdx.x % kWave;
-  const int hw = (blockIdx.x - 1) * kTrsvWaves + threadIdx.x / kWave;
-  const int HW = (gridDim.x - 1) * kTrsvWaves;
+  const int hw = (blockIdx.x - nmain) * kTrsvWaves + threadIdx.x / kWave;
+  const int HW = (gridDim.x - nmain) * kTrsvWaves;
   struct Rec {
     int4 r;
     bool ok;
@@ -413,9 +417,10 @@ __device__ __forceinline__ void trsv_helper(int nft, const int4 *__restrict__ ft
   }
 }
 
-// Block 0 is the main block, blocks 1.. are helpers. All blocks must be
-// resident at once (the grid is at most 1 + kMaxHelpers one-per-CU blocks);
-// every wait is bounded and reports through err.
+// Blocks 0..nmain-1 are main blocks (one when x is in LDS), the rest are
+// helpers. All blocks must be resident at once (the grid, one block per CU,
+// never exceeds the device's compute units); every wait is bounded and
+// reports through err.
 template <typename T, bool LDSX, int E>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
                                                        int nbatch,
@@ -424,11 +429,11 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__rest
                                                        const T *__restrict__ rhs, int nft, const int4 *__restrict__ ft,
                                                        const int32_t *__restrict__ fci, const T *__restrict__ fval,
                                                        T *__restrict__ x, T *__restrict__ far, int32_t *__restrict__ err,
-                                                       unsigned long long *__restrict__ trace) {
-  if (blockIdx.x == 0)
-    trsv_main<T, LDSX, E>(n, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
+                                                       int nmain, unsigned long long *__restrict__ trace) {
+  if ((int)blockIdx.x < nmain)
+    trsv_main<T, LDSX, E>(n, nmain, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
   else
-    trsv_helper<T>(nft, ft, fci, fval, x, far, err);
+    trsv_helper<T>(nmain, nft, ft, fci, fval, x, far, err);
 }
 
 // every x and far slot starts as the sentinel
@@ -884,7 +889,20 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
   const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
   k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
                                                                           (T *)c->farbuf);
-  const int helpers = (int)std::min<int64_t>(kMaxHelpers, (d.nft + kTrsvWaves - 1) / kTrsvWaves);
+  const int helpers =
+      (int)std::min<int64_t>(std::min(kMaxHelpers, c->ncu - 1), (d.nft + kTrsvWaves - 1) / kTrsvWaves);
+  // x in global memory: enough main blocks that each wave holds about half
+  // a batch of an average level (on a 100k-unknown graph Laplacian, 64 main
+  // blocks beat 32 by 1.4x and match 160), within the blocks the device
+  // keeps resident; LSQ_TRSV_MAIN_BLOCKS=<k> overrides the count
+  int nmain = 1;
+  if (!LDSX) {
+    const int64_t nlev = std::max<int64_t>(1, &d == &c->tri_b ? c->nlev_b : c->nlev_f);
+    int64_t want = (d.nbatch / nlev + kTrsvWaves / 2 - 1) / (kTrsvWaves / 2);
+    static const char *env_main = getenv("LSQ_TRSV_MAIN_BLOCKS");
+    if (env_main && atoi(env_main) > 0) want = atoi(env_main);
+    nmain = (int)std::max<int64_t>(1, std::min<int64_t>(want, c->ncu - helpers));
+  }
   // diagnostics: LSQ_TRSV_TRACE=<file> appends per-row shader-clock stamps of
   // every triangular solve (header: n, batches, rows per batch, 0; per task
   // slot 8 words: start, late-entry start, publish, level, late entries in,
@@ -896,10 +914,10 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
     if (hipMalloc(&trace, 8 * slots * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
     if (trace) (void)hipMemsetAsync(trace, 0, 8 * slots * sizeof(unsigned long long), c->stream);
   }
-  kern<<<1 + helpers, kTrsvThreads, lds, c->stream>>>((int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci,
-                                                      (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft, d.ft,
-                                                      d.fci, (const T *)d.fval, x, (T *)c->farbuf, c->flags + 3,
-                                                      trace);
+  kern<<<nmain + helpers, kTrsvThreads, lds, c->stream>>>((int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci,
+                                                          (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft,
+                                                          d.ft, d.fci, (const T *)d.fval, x, (T *)c->farbuf,
+                                                          c->flags + 3, nmain, trace);
   if (trace) {
     std::vector<unsigned long long> h(8 * slots);
     if (hipMemcpyAsync(h.data(), trace, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream) ==

@@ -411,7 +411,9 @@ static int setup_impl(lsq_ctx *ctx) {
       ALLOC(As, float, std::max<int64_t>(ctx->s_d, 1) * n);
       ALLOC(ctx->Mf, float, n * n);
       launch_gather_dense_f32(ctx, As, st);
+      const int gslot = prof_begin(ctx, KC_GRAM);
       launch_syrk_f32(ctx->s_d, n, As, ctx->Mf, st);
+      prof_end(ctx, gslot, (double)ctx->s_d * (double)n * (double)(n + 1));
       launch_dense_diag_guard_f32(n, ctx->Mf, ctx->flags, st);
       LSQ_HIP_CHECK(hipStreamSynchronize(st));
       lsq_free_one(ctx, As);
@@ -420,7 +422,9 @@ static int setup_impl(lsq_ctx *ctx) {
       ALLOC(As, double, std::max<int64_t>(ctx->s_d, 1) * n);
       ALLOC(ctx->Md, double, n * n);
       launch_gather_dense_f64(ctx, As, st);
+      const int gslot = prof_begin(ctx, KC_GRAM);
       launch_syrk_f64(ctx->s_d, n, As, ctx->Md, st);
+      prof_end(ctx, gslot, (double)ctx->s_d * (double)n * (double)(n + 1));
       launch_dense_diag_guard_f64(n, ctx->Md, ctx->flags, st);
       LSQ_HIP_CHECK(hipStreamSynchronize(st));
       lsq_free_one(ctx, As);
@@ -521,7 +525,8 @@ extern "C" int lsq_setup(const lsq_matrix *A, const double *b, double C, int32_t
   ctx->sweeps = sweeps;
   ctx->seed = seed;
   ctx->atap_algo = o.atap_algo;
-  if (hipGetDevice(&ctx->device) != hipSuccess) {
+  if (hipGetDevice(&ctx->device) != hipSuccess ||
+      hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) {
     delete ctx;
     return LSQ_EHIP;
   }

@@ -46,9 +46,9 @@ class Options(C.Structure):
 
 
 class KernelStats(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * 5), ("ms", C.c_double * 5), ("bytes", C.c_double * 5)]
 
-    CLASSES = ("trsv", "sgs_rhs", "atap", "vec")
+    CLASSES = ("trsv", "sgs_rhs", "atap", "vec", "gram")  # "gram": bytes holds flops
 
     def as_dict(self) -> dict:
         return {name: dict(launches=int(self.launches[i]), ms=float(self.ms[i]), bytes=float(self.bytes[i]))

@@ -295,3 +295,23 @@ def test_autograd_function():
     G = np.outer(r, lam) - np.outer(A @ lam, xd)
     rows = np.repeat(np.arange(p.m), np.diff(p.row_ptr))
     assert rel(vals.grad.cpu().numpy(), G[rows, p.col_idx]) <= 1e-8
+
+
+@pytest.mark.parametrize("nv,ne,mode", [(25000, 250_000, "fp64"), (45000, 300_000, "fp32_refine")])
+def test_triangular_solves_with_x_in_global_memory(nv, ne, mode):
+    """n beyond what the solve's x vector fits in LDS (150 KB): the main blocks
+    share the level batches and poll x in global memory."""
+    import torch
+    print("\n[global-x case] nv=%d ne=%d %s" % (nv, ne, mode), flush=True)
+    p = er_incidence(nv, ne, seed=8)
+    s, _ = make_solver(p, C_=4.0, sweeps=2, seed=0, mode=mode)
+    _, _, idx, _ = s.setup_arrays(want_w=False)
+    o = oracle.Oracle(p, C_=4.0, sweeps=2, seed=0, samples=idx)
+    if mode == "fp64":
+        r = np.random.default_rng(7).standard_normal(s.n)
+        z = s.apply_P(torch.from_numpy(r).cuda()).cpu().numpy()
+        assert rel(z, o.apply_P(r)) <= 1e-10
+    x, info = s.solve()
+    xo, _ = o.solve(tol=1e-10)
+    assert info["converged"] == 1 and info["relres_true"] <= 1e-10
+    assert rel(x.cpu().numpy(), xo) <= 1e-8

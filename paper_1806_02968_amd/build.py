@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsq.so")
 
-SOURCES = ["k_setup.hip", "k_gram.hip", "k_sgs.hip", "k_atap.hip", "k_vec.hip", "lsq_api.hip"]
+SOURCES = ["k_setup.hip", "k_gram.hip", "k_sgs.hip", "k_atap.hip", "k_transpose.hip", "k_vec.hip", "lsq_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",

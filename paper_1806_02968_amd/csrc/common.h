@@ -165,6 +165,14 @@ struct lsq_ctx {
 
   // sparse A^T(Ap) algorithm in use
   int atap_algo = 1;
+  // CSC copy of a sparse A (two-pass A^T(Ap), atap_algo 3): column pointers,
+  // row indices, values in A's storage type and, when the float32 inner solve
+  // reads a float32 copy of A, in float32; t = A u between the passes
+  int64_t *csc_cp = nullptr;
+  int32_t *csc_ri = nullptr;
+  void *csc_v = nullptr;
+  float *csc_v32 = nullptr;
+  double *tvec = nullptr;
 
   // kernel timing (opt.profile)
   static constexpr int kProfSlots = 64;
@@ -226,6 +234,7 @@ void sgs_apply_f32(lsq_ctx *c, const float *r, float *z);
 void atap_f64(lsq_ctx *c, const double *s_in, const double *p, const double *b, double *q,
               const double *s_out);
 void atap_f32(lsq_ctx *c, const float *s_in, const float *p, float *q, const float *s_out);
+int build_csc(lsq_ctx *ctx);  // k_transpose.hip
 // float64 residual pass: g = A^T (b - A x) (b may be null: g = -A^T A x)
 void resid64(lsq_ctx *c, const double *x, const double *b, double *g);
 // backward pass over A: grad_b = A lam, grad_A = (b - A x) lam^T - (A lam) x^T

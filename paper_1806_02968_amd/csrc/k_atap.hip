@@ -328,50 +328,106 @@ __global__ __launch_bounds__(kAtThreads) void k_gemv_t_part(int64_t m, int64_t n
 // ---------------------------------------------------------------------------
 // CSR
 
-template <typename TA, typename CT, int G, bool HAS_B, bool LDS>
+// One pass over rows [r0, r1) of a CSR matrix by groups of G lanes: group g
+// takes rows r0 + (it*U + u)*ngrp + g, U rows at a time, so the row pointers,
+// entries and b values of U rows are requested before any of them is used
+// (enough bytes in flight to cover the memory latency), and at each u the
+// groups of a block read one contiguous stretch of entries. For each row it
+// forms d = a_i . u (d = b_i - a_i . u with HAS_B), calls emit(i, d) on the
+// row's first lane and, with SCATTER, add(j, d a_ij) for its entries.
+template <typename TA, typename CT, int G, int U, bool HAS_B, bool SCATTER, int NT, typename Gather, typename Add,
+          typename Emit>
+__device__ __forceinline__ void csr_rows_pass(int64_t r0, int64_t r1, const int64_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci, const TA *__restrict__ v,
+                                              const double *__restrict__ b, Gather uget, Add add, Emit emit) {
+  constexpr int ngrp = NT / G;
+  const int gl = threadIdx.x % G;
+  const int grp = threadIdx.x / G;
+  for (int64_t base = r0; base < r1; base += (int64_t)ngrp * U) {
+    TA av[U];
+    int32_t aj[U];
+    double bv[U];
+    int onrows = 0;    // rows with an entry in this lane
+    int longrows = 0;  // rows with more than G entries (their rest is read again below)
+    // loads are issued unconditionally from clamped indices and their
+    // results selected afterwards: a guarded load becomes a branch with a
+    // wait for every earlier load
+    int64_t k0[U], k1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * ngrp + grp;
+      const int64_t ic = i < r1 ? i : r0;
+      k0[u] = rp[ic];
+      k1[u] = rp[ic + 1];
+      if (HAS_B) bv[u] = b[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = base + u * ngrp + grp < r1;
+      const int64_t len = (k1[u] - k0[u]) & -(int64_t)ok;
+      const bool on = gl < len;
+      const int64_t k = on ? k0[u] + gl : 0;
+      av[u] = v[k];
+      aj[u] = ci[k];
+      onrows |= on ? 1 << u : 0;
+      longrows |= len > G ? 1 << u : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = (onrows >> u) & 1 ? av[u] : (TA)0;
+      aj[u] = (onrows >> u) & 1 ? aj[u] : 0;
+    }
+    CT d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = (CT)av[u] * uget(aj[u]);
+    if (longrows) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!((longrows >> u) & 1)) continue;
+        const int64_t i = base + u * ngrp + grp;
+        const int64_t k1 = i < r1 ? rp[i + 1] : 0;
+        for (int64_t k = (i < r1 ? rp[i] : 0) + G + gl; k < k1; k += G) d[u] += (CT)v[k] * uget(ci[k]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      d[u] = group_sum<G>(d[u]);
+      if (HAS_B) d[u] = (CT)bv[u] - d[u];
+      const int64_t i = base + u * ngrp + grp;
+      if (gl == 0 && i < r1) emit(i, d[u]);
+    }
+    if (!SCATTER) continue;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if ((onrows >> u) & 1) add(aj[u], d[u] * (CT)av[u]);
+    if (longrows) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!((longrows >> u) & 1)) continue;
+        const int64_t i = base + u * ngrp + grp;
+        const int64_t k1 = i < r1 ? rp[i + 1] : 0;
+        for (int64_t k = (i < r1 ? rp[i] : 0) + G + gl; k < k1; k += G) add(ci[k], d[u] * (CT)v[k]);
+      }
+    }
+  }
+}
+
+// rows in flight per group: enough that a block has tens of KB of A requested
+template <int G>
+constexpr int csr_unroll() {
+  return G <= 16 ? 8 : (G == 32 ? 4 : 2);
+}
+
+template <typename TA, typename CT, int G, bool HAS_B>
 __global__ __launch_bounds__(kAtThreads) void k_atap_csr(int64_t m, int n, const int64_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci, const TA *__restrict__ v,
                                                          const CT *__restrict__ u, const double *__restrict__ b,
                                                          CT *__restrict__ q, int64_t rows_per_blk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  CT *qs = (CT *)smem;
-  if (LDS) {
-    for (int j = threadIdx.x; j < n; j += kAtThreads) qs[j] = 0;
-    __syncthreads();
-  }
-  const int gl = threadIdx.x % G;
-  const int grp = threadIdx.x / G;
-  constexpr int ngrp = kAtThreads / G;
   const int64_t r0 = blockIdx.x * rows_per_blk;
-  int64_t r1 = r0 + rows_per_blk;
-  if (r1 > m) r1 = m;
-  const int64_t iters = (rows_per_blk + ngrp - 1) / ngrp;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t i = r0 + grp + it * ngrp;
-    CT d = 0;
-    int64_t k0 = 0, k1 = 0;
-    if (i < r1) {
-      k0 = rp[i];
-      k1 = rp[i + 1];
-      for (int64_t k = k0 + gl; k < k1; k += G) d += (CT)v[k] * u[ci[k]];
-    }
-    d = group_sum<G>(d);
-    if (HAS_B && i < r1) d = (CT)b[i] - d;
-    if (i < r1) {
-      for (int64_t k = k0 + gl; k < k1; k += G) {
-        const CT add = d * (CT)v[k];
-        if (LDS) atomicAdd(&qs[ci[k]], add);
-        else atomicAdd(&q[ci[k]], add);
-      }
-    }
-  }
-  if (LDS) {
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += kAtThreads) {
-      const CT s = qs[j];
-      if (s != (CT)0) atomicAdd(&q[j], s);
-    }
-  }
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  csr_rows_pass<TA, CT, G, csr_unroll<G>(), HAS_B, true, kAtThreads>(
+      r0, r1, rp, ci, v, b, [&](int j) -> CT { return u[j]; }, [&](int j, CT a) { atomicAdd(&q[j], a); },
+      [](int64_t, CT) {});
 }
 
 // per-workgroup accumulation in LDS; each workgroup writes one partial output
@@ -393,29 +449,29 @@ __global__ __launch_bounds__(kLdsThreads) void k_atap_csr_lds(int64_t m, int n, 
   }
   __syncthreads();
   const CT *u = USTAGE ? us : ug;
-  const int gl = threadIdx.x % G;
-  const int grp = threadIdx.x / G;
-  constexpr int ngrp = kLdsThreads / G;
   const int64_t r0 = blockIdx.x * rows_per_blk;
-  int64_t r1 = r0 + rows_per_blk;
-  if (r1 > m) r1 = m;
-  const int64_t iters = (rows_per_blk + ngrp - 1) / ngrp;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t i = r0 + grp + it * ngrp;
-    CT d = 0;
-    int64_t k0 = 0, k1 = 0;
-    if (i < r1) {
-      k0 = rp[i];
-      k1 = rp[i + 1];
-      for (int64_t k = k0 + gl; k < k1; k += G) d += (CT)v[k] * u[ci[k]];
-    }
-    d = group_sum<G>(d);
-    if (HAS_B && i < r1) d = (CT)b[i] - d;
-    if (i < r1)
-      for (int64_t k = k0 + gl; k < k1; k += G) atomicAdd(&qs[ci[k]], d * (CT)v[k]);
-  }
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  csr_rows_pass<TA, CT, G, csr_unroll<G>(), HAS_B, true, kLdsThreads>(
+      r0, r1, rp, ci, v, b, [&](int j) -> CT { return u[j]; }, [&](int j, CT a) { atomicAdd(&qs[j], a); },
+      [](int64_t, CT) {});
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += kLdsThreads) part[blockIdx.x * (int64_t)n + j] = qs[j];
+}
+
+// one row pass without scatter: out_i = scale_i * (hb b_i - a_i . u), for the
+// two-pass product (rows of A with u = D^{-1} p, then rows of the CSC copy,
+// i.e. columns of A, with u = t)
+template <typename TA, typename CT, typename UT, int G, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_csr_dot(int64_t m, const int64_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci, const TA *__restrict__ v,
+                                                        const UT *__restrict__ u, const double *__restrict__ b,
+                                                        const CT *__restrict__ scale, UT *__restrict__ out,
+                                                        int64_t rows_per_blk) {
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  csr_rows_pass<TA, CT, G, csr_unroll<G>(), HAS_B, false, kAtThreads>(
+      r0, r1, rp, ci, v, b, [&](int j) -> CT { return (CT)u[j]; }, [](int, CT) {},
+      [&](int64_t i, CT d) { out[i] = (UT)(scale ? scale[i] * d : d); });
 }
 
 template <typename CT>
@@ -547,18 +603,52 @@ static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
     k_part_reduce<CT><<<dim3((unsigned)(fb > 0 ? fb : 1), (unsigned)nseg), 256, 0, st>>>(n, part, (int)nblk, seg, part2);
     k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part2, nseg, nullptr, q);
   } else {
-    const int64_t rows_per_grp_iter = kAtThreads / G;
-    int64_t nblk = (m + rows_per_grp_iter * 4 - 1) / (rows_per_grp_iter * 4);
+    const int64_t rows_per_blk_iter = (kAtThreads / G) * csr_unroll<G>();
+    int64_t nblk = (m + rows_per_blk_iter - 1) / rows_per_blk_iter;
     if (nblk > 65536) nblk = 65536;
     if (nblk < 1) nblk = 1;
     const int64_t rpb = (m + nblk - 1) / nblk;
-    k_atap_csr<TA, CT, G, HAS_B, false><<<(unsigned)nblk, kAtThreads, 0, st>>>(m, n, c->rp, c->ci, v, u, b, q, rpb);
+    k_atap_csr<TA, CT, G, HAS_B><<<(unsigned)nblk, kAtThreads, 0, st>>>(m, n, c->rp, c->ci, v, u, b, q, rpb);
   }
+}
+
+template <typename TA, typename CT, bool HAS_B, int G>
+static void csr_dot_g(int64_t rows, const int64_t *rp, const int32_t *ci, const TA *v, const CT *u, const double *b,
+                      const CT *scale, CT *out, hipStream_t st) {
+  const int64_t rows_per_blk_iter = (kAtThreads / G) * csr_unroll<G>();
+  int64_t nblk = (rows + rows_per_blk_iter - 1) / rows_per_blk_iter;
+  if (nblk > 65536) nblk = 65536;
+  if (nblk < 1) nblk = 1;
+  const int64_t rpb = (rows + nblk - 1) / nblk;
+  k_csr_dot<TA, CT, CT, G, HAS_B><<<(unsigned)nblk, kAtThreads, 0, st>>>(rows, rp, ci, v, u, b, scale, out, rpb);
+}
+
+// out_i = scale_i (hb b_i - a_i . u) over the rows of a CSR matrix, G lanes
+// per row chosen by the average row length
+template <typename TA, typename CT, bool HAS_B>
+static void csr_dot(int64_t rows, int64_t nnz, const int64_t *rp, const int32_t *ci, const TA *v, const CT *u,
+                    const double *b, const CT *scale, CT *out, hipStream_t st) {
+  const double avg = (double)nnz / (double)(rows > 0 ? rows : 1);
+  if (avg <= 2) csr_dot_g<TA, CT, HAS_B, 2>(rows, rp, ci, v, u, b, scale, out, st);
+  else if (avg <= 4) csr_dot_g<TA, CT, HAS_B, 4>(rows, rp, ci, v, u, b, scale, out, st);
+  else if (avg <= 8) csr_dot_g<TA, CT, HAS_B, 8>(rows, rp, ci, v, u, b, scale, out, st);
+  else if (avg <= 16) csr_dot_g<TA, CT, HAS_B, 16>(rows, rp, ci, v, u, b, scale, out, st);
+  else if (avg <= 32) csr_dot_g<TA, CT, HAS_B, 32>(rows, rp, ci, v, u, b, scale, out, st);
+  else csr_dot_g<TA, CT, HAS_B, 64>(rows, rp, ci, v, u, b, scale, out, st);
 }
 
 template <typename TA, typename CT, bool HAS_B>
 static void atap_csr_t(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, const CT *s_out) {
   hipStream_t st = c->stream;
+  if (c->atap_algo == 3) {
+    // two passes: t = hb b - A u over the rows, q = s_out (A^T t) over the
+    // columns (the CSC copy of the values that v points at)
+    const TA *cv = (const void *)v == c->A ? (const TA *)c->csc_v : (const TA *)(const void *)c->csc_v32;
+    CT *t = (CT *)(void *)c->tvec;
+    csr_dot<TA, CT, HAS_B>(c->m, c->nnz, c->rp, c->ci, v, u, b, nullptr, t, st);
+    csr_dot<TA, CT, false>(c->n, c->nnz, c->csc_cp, c->csc_ri, cv, t, nullptr, s_out, q, st);
+    return;
+  }
   const bool lds = c->atap_algo == 2;
   if (!lds) {
     if (sizeof(CT) == 8) launch_fill_f64((double *)q, c->n, 0.0, st);

@@ -323,9 +323,13 @@ static int setup_impl(lsq_ctx *ctx) {
   ALLOC(ctx->cdf, double, m);
   // reduction partials and dense A^T(Ap) partial rows
   // sparse A^T(Ap): per-workgroup LDS partial rows when a row of n values fits
-  // in LDS, global atomics otherwise
-  if (ctx->opt.atap_algo == 0) ctx->atap_algo = n * 8 <= 131072 ? 2 : 1;
-  if (ctx->atap_algo == 2 && n * 8 > 131072) ctx->atap_algo = 1;
+  // in LDS, otherwise two passes over A (rows, then a CSC copy), or global
+  // atomics on request
+  const bool csc_ok = ctx->fmt == LSQ_CSR && m < INT32_MAX;
+  if (ctx->opt.atap_algo == 0 && ctx->fmt == LSQ_CSR) ctx->atap_algo = n * 8 <= 131072 ? 2 : (csc_ok ? 3 : 1);
+  if (ctx->opt.atap_algo == 0 && ctx->fmt == LSQ_DENSE) ctx->atap_algo = n * 8 <= 131072 ? 2 : 1;
+  if (ctx->fmt == LSQ_CSR && ctx->atap_algo == 2 && n * 8 > 131072) ctx->atap_algo = csc_ok ? 3 : 1;
+  if (ctx->fmt == LSQ_CSR && ctx->atap_algo == 3 && !csc_ok) ctx->atap_algo = 1;
   const int64_t part_elems = std::max<int64_t>(
       ctx->fmt == LSQ_DENSE ? (1024 + 64) * n : (ctx->atap_algo == 2 ? (256 + 16) * n : n), 4096);
   ALLOC(ctx->part, double, part_elems);
@@ -452,6 +456,7 @@ static int setup_impl(lsq_ctx *ctx) {
       ctx->A32 = ctx->A32own;
     }
   }
+  if (ctx->fmt == LSQ_CSR && ctx->atap_algo == 3) TRY(build_csc(ctx));
 
   // work vectors
   ALLOC(ctx->vy, double, n);

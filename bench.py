@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--atap-algo", type=int, default=0)
     ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
+    ap.add_argument("--chain-levels", type=int, default=0,
+                    help="triangular-solve chain wave levels (0: library default, -1: chain mode off)")
     ap.add_argument("--max-iter", type=int, default=0, help="PCG iteration cap (0: library default, 10 n)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device twice (HBM counter calibration) and exit")
@@ -97,11 +99,13 @@ def main():
     def step(mode, profile):
         if p.fmt == "dense":
             s = Solver(dev["A"], b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
-                       atap_algo=args.atap_algo, near_levels=args.near_levels, max_iter=args.max_iter)
+                       atap_algo=args.atap_algo, near_levels=args.near_levels,
+                       chain_levels=args.chain_levels, max_iter=args.max_iter)
         else:
             s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
                        b=b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
-                       atap_algo=args.atap_algo, near_levels=args.near_levels, max_iter=args.max_iter)
+                       atap_algo=args.atap_algo, near_levels=args.near_levels,
+                       chain_levels=args.chain_levels, max_iter=args.max_iter)
         x, info = s.solve()
         ks = s.kernel_stats() if profile else None
         s.close()

@@ -93,6 +93,10 @@ typedef struct {
                           many levels below their own row's level are summed on
                           the dependency chain, older ones ahead of time on
                           other CUs (0: 48; at most 1024)                    */
+  int32_t chain_levels; /* triangular solves: when x and the rows' partial sums
+                          fit in LDS and levels hold few rows, one wave sums
+                          the entries reading rows at most this many levels
+                          below (0: 6; -1: off; at most 64)                   */
 } lsq_options;
 
 /* Fills *opt with the defaults above. */

@@ -100,6 +100,10 @@ struct TriDev {
   int32_t *mci = nullptr, *fci = nullptr;
   void *mval = nullptr, *fval = nullptr;
   int64_t nbatch = 0, nft = 0, nslot = 0;
+  // chain mode: per pass and lane the row and the chain entries
+  int32_t *crow = nullptr, *cj = nullptr;
+  void *cv = nullptr;
+  int64_t npass = 0;
 };
 
 struct lsq_ctx {
@@ -141,6 +145,8 @@ struct lsq_ctx {
   // triangle's entries copied in task order (values in the solve's precision)
   int G = 64;  // lanes per row in the strict-part products
   int trsv_e = 4;  // near entries per lane of the triangular solves' main block
+  bool trsv_chain = false;  // chain mode of the triangular solves
+  int trsv_ec = 2;          // chain entries per lane (chain mode)
   TriDev tri_f, tri_b;
   void *tdg = nullptr;     // diagonal of M
   void *farbuf = nullptr;  // far-sum slots

@@ -42,7 +42,10 @@ struct Bits<float> {
   static constexpr U kSent = 0x7FA0BEEFu;
 };
 
-constexpr int kTrsvThreads = 1024, kTrsvWaves = kTrsvThreads / kWave;
+#ifndef LSQ_TRSV_THREADS
+#define LSQ_TRSV_THREADS 1024
+#endif
+constexpr int kTrsvThreads = LSQ_TRSV_THREADS, kTrsvWaves = kTrsvThreads / kWave;
 #ifndef LSQ_MAIN_G
 #define LSQ_MAIN_G 16
 #endif
@@ -52,6 +55,20 @@ constexpr int kFarE = 8, kFarChunk = kWave * kFarE;               // helpers: on
 // up to kLateLanes lanes per row.
 constexpr int kLateLevels = 1, kLateLanes = 4;
 constexpr int kMaxHelpers = 32;
+// Chain mode (x and the rows' bases both fit in LDS): one wave of a
+// kChainThreads-thread main block takes the entries of the kChainLevels
+// levels below each row itself, kChainRows rows of a level per pass with
+// kChainLanes lanes per row; the block's other waves compute the bases.
+// clock stamps of the triangular solves, a diagnostic build only (reading
+// the clock slows the solve even when no stamp is written)
+#ifndef LSQ_TRSV_STAMPS
+#define LSQ_TRSV_STAMPS 0
+#endif
+#ifndef LSQ_CHAIN_THREADS
+#define LSQ_CHAIN_THREADS 512
+#endif
+constexpr int kChainThreads = LSQ_CHAIN_THREADS, kChainLanes = 4, kChainRows = kWave / kChainLanes;
+constexpr int kMaxChainHelpers = 64;
 constexpr int kSpinLimit = 1 << 22;
 
 // wave priorities of the main block: default, while polling, on the chain
@@ -133,7 +150,7 @@ __device__ __forceinline__ MainTask main_task(int bt, int g, int nbatch, const i
 // polled until it does not; rows of one level may finish in any order.
 // Batches are in level order and each wave takes its batches in order, so
 // the earliest unfinished batch only reads finished rows and can finish.
-template <typename T, bool LDSX, int E>
+template <typename T, bool LDSX, int E, bool CHAIN = false, int NT = kTrsvThreads>
 __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restrict__ ta, const int4 *__restrict__ tb,
                                           int nbatch, const int32_t *__restrict__ mci, const T *__restrict__ mval,
                                           const T *__restrict__ diag, const T *__restrict__ rhs, T *__restrict__ x,
@@ -144,16 +161,19 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
   constexpr int scope = LDSX ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
   extern __shared__ __align__(16) unsigned char smem[];
   T *xs = LDSX ? (T *)smem : x;
+  T *bs = xs + n;  // chain mode: the rows' bases, in LDS after x
   // x slots hold the sentinel until written (the global copy was reset
-  // before the launch)
-  if (LDSX) {
-    for (int i = threadIdx.x; i < n; i += kTrsvThreads) ((U *)xs)[i] = Bits<T>::kSent;
+  // before the launch); in chain mode the kernel has set the LDS slots
+  if (LDSX && !CHAIN) {
+    for (int i = threadIdx.x; i < n; i += NT) ((U *)xs)[i] = Bits<T>::kSent;
     __syncthreads();
   }
   // with x in global memory several main blocks share the batches: wave w
-  // of all main blocks takes batches w, w + NW, ...
-  const int wave = blockIdx.x * kTrsvWaves + threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int NW = nmain * kTrsvWaves;
+  // of all main blocks takes batches w, w + NW, ...; in chain mode wave 0 of
+  // the block is the chain and the others take the batches
+  constexpr int WW = NT / kWave - (CHAIN ? 1 : 0);
+  const int wave = blockIdx.x * WW + threadIdx.x / kWave - (CHAIN ? 1 : 0), lane = threadIdx.x % kWave;
+  const int NW = nmain * WW;
   const int g = lane / G, gl = lane % G;
   const int li = G - 1 - gl;  // late lanes: li < Q (the writer, lane G-1, is li = 0)
   __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
@@ -185,7 +205,7 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
       mask |= ok ? (1 << e) : 0;
     }
     d.mask = mask | (row >= 0 && k1 - k0 > G * E ? (1 << E) : 0);
-    const int nl = row >= 0 ? t.a.w : 0, nf = row >= 0 ? t.b.w : 0;
+    const int nl = row >= 0 && !CHAIN ? t.a.w : 0, nf = row >= 0 ? t.b.w : 0;
     const int lk = li < Q && li < nl ? k1 + li : 0;
     d.lj = mci[lk];
     d.lv = mval[lk];
@@ -240,7 +260,7 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
     return __builtin_bit_cast(T, u);
   };
   auto consume = [&](const Buf &d, int bt) {
-    const unsigned long long t_in = trace ? __builtin_readcyclecounter() : 0;
+    const unsigned long long t_in = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
     const int slot = bt * R + g;
     // near entries: their rows are normally written long before
     U xu[E];
@@ -269,27 +289,32 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
     for (int q = G + gl; q < d.nf; q += G) acc += far_value(d.f0 + q, ld_sync(far + d.f0 + q));
     acc = dpp_group_sum<G>(acc);  // every lane of the row holds the sum
     T base = d.rv / d.dg - acc;
+    if (CHAIN) {  // the chain wave adds the rest
+      if (d.row >= 0 && gl == G - 1)
+        __hip_atomic_store((U *)bs + d.row, __builtin_bit_cast(U, base), __ATOMIC_RELAXED, scope);
+      return;
+    }
     __asm__ volatile("" : "+v"(base));  // computed here, off the chain
     // late entries: the dependency chain
-    const unsigned long long t_go = trace ? __builtin_readcyclecounter() : 0;
+    const unsigned long long t_go = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
     const bool lon = li < Q && li < d.nl;
     T lacc = 0;
     if (lon) lacc = d.lv * late_x(d.lj);
-    const unsigned long long t_read = trace ? __builtin_readcyclecounter() : 0;
+    const unsigned long long t_read = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
     if (d.nl > Q) {  // more than Q late entries (rare)
       const int4 a = ta[slot];
       for (int k = a.z + Q + li; li < Q && k < a.z + d.nl; k += Q) lacc += mval[k] * late_x(mci[k]);
     }
     if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_LATE);
-    const unsigned long long t_ready = trace ? __builtin_readcyclecounter() : 0;
+    const unsigned long long t_ready = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
     lacc = dpp_group_sum<Q>(lacc);
     if (d.row >= 0 && gl == G - 1) {
       const T xi = base - lacc;
       if (LDSX) __hip_atomic_store((U *)xs + d.row, __builtin_bit_cast(U, xi), __ATOMIC_RELAXED, scope);
-      const unsigned long long t_pub = trace ? __builtin_readcyclecounter() : 0;
+      const unsigned long long t_pub = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
       st_sync(x + d.row, xi);
       if (LSQ_WAKEUP) __asm__ volatile("s_wakeup");
-      if (trace) {  // diagnostics (shader clock): start, late start, publish, level
+      if (LSQ_TRSV_STAMPS && trace) {  // diagnostics (shader clock): start, late start, publish, level
         trace[8 * slot] = t_in;
         trace[8 * slot + 1] = t_go;
         trace[8 * slot + 2] = t_pub;
@@ -327,7 +352,7 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
 }
 
 // Helper waves: far-chunk q is taken by helper wave q mod HW, in level order.
-template <typename T>
+template <typename T, int NT = kTrsvThreads>
 __device__ __forceinline__ void trsv_helper(int nmain, int nft, const int4 *__restrict__ ft,
                                             const int32_t *__restrict__ fci,
                                             const T *__restrict__ fval, const T *__restrict__ x, T *__restrict__ far,
@@ -335,8 +360,8 @@ __device__ __forceinline__ void trsv_helper(int nmain, int nft, const int4 *__re
   typedef typename Bits<T>::U U;
   constexpr int E = kFarE;
   const int lane = threadIdx.x % kWave;
-  const int hw = (blockIdx.x - nmain) * kTrsvWaves + threadIdx.x / kWave;
-  const int HW = (gridDim.x - nmain) * kTrsvWaves;
+  const int hw = (blockIdx.x - nmain) * (NT / kWave) + threadIdx.x / kWave;
+  const int HW = (gridDim.x - nmain) * (NT / kWave);
   struct Rec {
     int4 r;
     bool ok;
@@ -434,6 +459,126 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__rest
     trsv_main<T, LDSX, E>(n, nmain, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, trace);
   else
     trsv_helper<T>(nmain, nft, ft, fci, fval, x, far, err);
+}
+
+// The chain wave of chain mode. Pass p holds up to kChainRows rows of one
+// level (level order), kChainLanes lanes per row: crow[p][lane] is the row of
+// the lane's group (-1: none), cj/cv[p][e][lane] entry q + 4e (q = lane % 4)
+// of the row's chain part (column -1: none; pass npass is empty), i.e. the
+// entries reading rows at
+// most kChainLevels levels below. Those rows were all written by this wave
+// in earlier passes, and LDS accesses of one wave complete in order, so
+// their x values are read without polling. x_i = base_i - (chain sum), with
+// base_i (r_i / M_ii minus the near and far sums) published in LDS by the
+// block's other waves, normally well before the chain gets there.
+template <typename T, int EC>
+__device__ __forceinline__ void trsv_chain(int npass, const int32_t *__restrict__ crow, const int32_t *__restrict__ cj,
+                                           const T *__restrict__ cv, T *xs, T *bs, T *__restrict__ x,
+                                           int32_t *__restrict__ err, unsigned long long *__restrict__ trace) {
+  typedef typename Bits<T>::U U;
+  constexpr int PD = 6;  // passes in registers: loads run PD - 1 passes ahead
+  const int lane = threadIdx.x % kWave;
+  __builtin_amdgcn_s_setprio(3);
+  struct CB {
+    int row;
+    int j[EC];
+    T v[EC];
+  };
+  auto lds_ld = [&](T *a, int i) -> U {
+    return __hip_atomic_load((U *)a + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  // passes past the last read the empty pass npass; nothing computed from a
+  // loaded value here (that would wait for the load)
+  auto load = [&](int p, CB &c) {
+    const int64_t pp = p < npass ? p : npass;
+    c.row = crow[pp * kWave + lane];
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      c.j[e] = cj[(pp * EC + e) * kWave + lane];
+      c.v[e] = cv[(pp * EC + e) * kWave + lane];
+    }
+  };
+  auto run = [&](const CB &c, int p) {
+    const unsigned long long t0 = LSQ_TRSV_STAMPS ? __builtin_readcyclecounter() : 0;
+    const bool on = c.row >= 0;
+    U bu = lds_ld(bs, on ? c.row : 0);
+    T pr[EC];
+#pragma unroll
+    for (int e = 0; e < EC; ++e) {
+      const bool ok = c.j[e] >= 0;
+      const U xu = lds_ld(xs, ok ? c.j[e] : 0);
+      pr[e] = ok ? c.v[e] * __builtin_bit_cast(T, xu) : (T)0;
+    }
+#pragma unroll
+    for (int w = 1; w < EC; w *= 2)  // pairwise sum of the lane's products
+#pragma unroll
+      for (int e = 0; e + w < EC; e += 2 * w) pr[e] += pr[e + w];
+    if (on && bu == Bits<T>::kSent) {  // base not yet published
+      int spins = 0;
+      do {
+        if (give_up(spins, err)) {
+          bu = 0;
+          break;
+        }
+        bu = lds_ld(bs, c.row);
+      } while (bu == Bits<T>::kSent);
+    }
+    const unsigned long long t1 = LSQ_TRSV_STAMPS ? __builtin_readcyclecounter() : 0;
+    const T acc = dpp_group_sum<kChainLanes>(pr[0]);
+    const T xi = __builtin_bit_cast(T, bu) - acc;
+    if (on && lane % kChainLanes == 0) {
+      __hip_atomic_store((U *)xs + c.row, __builtin_bit_cast(U, xi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      st_sync(x + c.row, xi);
+    }
+    if (LSQ_TRSV_STAMPS && trace && lane == 0 && p < npass) {  // diagnostics (shader clock)
+      trace[4 * p] = t0;
+      trace[4 * p + 1] = t1;
+      trace[4 * p + 2] = __builtin_readcyclecounter();
+      trace[4 * p + 3] = (unsigned long long)c.row;
+    }
+  };
+  // the prologue issues passes in order, as the loop does, so that one wait
+  // count per use fits every trip
+  CB C[PD];
+#pragma unroll
+  for (int s = 0; s < PD - 1; ++s) {
+    load(s, C[s]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const int trips = (npass + PD - 1) / PD;
+  for (int it = 0, p = 0; it < trips; ++it, p += PD) {
+#pragma unroll
+    for (int s = 0; s < PD; ++s) {
+      load(p + s + PD - 1, C[(s + PD - 1) % PD]);
+      __builtin_amdgcn_sched_barrier(0);
+      run(C[s], p + s);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Chain mode: block 0 holds x and the bases in LDS; its wave 0 is the chain,
+// its other waves compute the bases; blocks 1.. are helpers.
+template <typename T, int E, int EC>
+__global__ __launch_bounds__(kChainThreads) void k_trsv_chain(
+    int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb, int nbatch, const int32_t *__restrict__ mci,
+    const T *__restrict__ mval, const T *__restrict__ diag, const T *__restrict__ rhs, int nft,
+    const int4 *__restrict__ ft, const int32_t *__restrict__ fci, const T *__restrict__ fval, int npass,
+    const int32_t *__restrict__ crow, const int32_t *__restrict__ cj, const T *__restrict__ cv, T *__restrict__ x,
+    T *__restrict__ far, int32_t *__restrict__ err, unsigned long long *__restrict__ trace) {
+  typedef typename Bits<T>::U U;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.x == 0) {
+    T *xs = (T *)smem;
+    for (int i = threadIdx.x; i < 2 * n; i += kChainThreads) ((U *)xs)[i] = Bits<T>::kSent;
+    __syncthreads();
+    if (threadIdx.x < kWave)
+      trsv_chain<T, EC>(npass, crow, cj, cv, xs, xs + n, x, err, trace);
+    else
+      trsv_main<T, true, E, true, kChainThreads>(n, 1, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, nullptr);
+  } else {
+    trsv_helper<T, kChainThreads>(1, nft, ft, fci, fval, x, far, err);
+  }
 }
 
 // every x and far slot starts as the sentinel
@@ -573,10 +718,12 @@ __device__ __forceinline__ void row_bounds(bool upper, int n, int i, const int32
   }
 }
 
-__device__ __forceinline__ int entry_class(int dl, int D) { return dl <= kLateLevels ? 1 : (dl <= D ? 0 : 2); }
+// 1: late (read on the dependency chain: the K levels below, K = 1 unless
+// in chain mode), 0: near (up to D levels below), 2: far
+__device__ __forceinline__ int entry_class(int dl, int K, int D) { return dl <= K ? 1 : (dl <= D ? 0 : 2); }
 
 template <bool DENSE>
-__global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int D, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int K, int D, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
                                                      const int32_t *__restrict__ lev, int4 *__restrict__ cnt) {
   const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
@@ -588,7 +735,7 @@ __global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int D, c
   int c0 = 0, c1 = 0, c2 = 0;
   for (int64_t k = a + lane; k < b; k += kWave) {
     const int j = DENSE ? (int)(k - (int64_t)i * n) : ci[k];
-    const int cl = entry_class(li - lev[j], D);
+    const int cl = entry_class(li - lev[j], K, D);
     c0 += cl == 0;
     c1 += cl == 1;
     c2 += cl == 2;
@@ -603,7 +750,7 @@ __global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int D, c
 // position info[i].x, far entries at far position info[i].y, each class in
 // column order (wave-wide ballot ranks).
 template <typename T, bool DENSE>
-__global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, int D, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, int K, int D, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
                                                        const T *__restrict__ val, const int32_t *__restrict__ lev,
                                                        const int4 *__restrict__ cnt, const int4 *__restrict__ info,
@@ -622,7 +769,7 @@ __global__ __launch_bounds__(256) void k_split_scatter(int n, bool upper, int D,
     const int64_t k = k0 + lane;
     const bool on = k < b;
     const int j = on ? (DENSE ? (int)(k - (int64_t)i * n) : ci[k]) : 0;
-    const int cl = on ? entry_class(li - lev[j], D) : 3;
+    const int cl = on ? entry_class(li - lev[j], K, D) : 3;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const unsigned long long m = __ballot(cl == t);
@@ -659,6 +806,26 @@ __global__ __launch_bounds__(256) void k_far_probe(int nft, int4 *__restrict__ f
     key = o > key ? o : key;
   }
   if (lane == 0) ft[c].w = (int)(key & 0x7FFFFFFF);
+}
+
+// chain passes from (row, first chain entry, chain entries) per row group
+template <typename T>
+__global__ __launch_bounds__(256) void k_chain_pack(int npass, int ec, const int4 *__restrict__ cq,
+                                                    const int32_t *__restrict__ mci, const T *__restrict__ mval,
+                                                    int32_t *__restrict__ crow, int32_t *__restrict__ cj,
+                                                    T *__restrict__ cv) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)npass * kWave) return;
+  const int64_t p = t / kWave;
+  const int lane = (int)(t % kWave);
+  const int4 q = cq[p * kChainRows + lane / kChainLanes];
+  crow[t] = q.x;
+  for (int e = 0; e < ec; ++e) {
+    const int k = lane % kChainLanes + kChainLanes * e;
+    const bool ok = q.x >= 0 && k < q.z;
+    cj[(p * ec + e) * kWave + lane] = ok ? mci[q.y + k] : -1;
+    cv[(p * ec + e) * kWave + lane] = ok ? mval[q.y + k] : (T)0;
+  }
 }
 
 // diagonal of M in the solve's precision
@@ -725,21 +892,6 @@ int build_levels(lsq_ctx *ctx) {
     LSQ_HIP_CHECK(hipMemcpyAsync(lev_f.data(), dlev_f, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ_HIP_CHECK(hipMemcpyAsync(lev_b.data(), dlev_b, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   }
-  // entry counts per row and class
-  int4 *dcnt;
-  if ((rc = alloc(2 * n * sizeof(int4), (void **)&dcnt)) != LSQ_OK) return rc;
-  const unsigned rows_grid = (unsigned)((n * kWave + 255) / 256);
-  for (int u = 0; u < 2; ++u) {
-    const int32_t *lv = u ? dlev_b : dlev_f;
-    if (dense)
-      k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, D, nullptr, nullptr, nullptr, lv, dcnt + u * n);
-    else
-      k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, D, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
-                                                      dcnt + u * n);
-  }
-  LSQ_HIP_CHECK(hipGetLastError());
-  std::vector<int4> hcnt(2 * n);
-  LSQ_HIP_CHECK(hipMemcpyAsync(hcnt.data(), dcnt, 2 * n * sizeof(int4), hipMemcpyDeviceToHost, st));
   LSQ_HIP_CHECK(hipStreamSynchronize(st));
   int32_t hflag = 0;
   LSQ_HIP_CHECK(hipMemcpy(&hflag, ctx->flags + 3, sizeof(hflag), hipMemcpyDeviceToHost));
@@ -747,10 +899,53 @@ int build_levels(lsq_ctx *ctx) {
     ctx->err = "level analysis wait limit exceeded";
     return LSQ_EHIP;
   }
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  // chain mode when x and the bases fit in LDS and levels are narrow (a few
+  // chain passes per level)
+  int K = 1;
+  {
+    int32_t Lf = 0, Lb = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      Lf = std::max(Lf, lev_f[i] + 1);
+      Lb = std::max(Lb, lev_b[i] + 1);
+    }
+    const int kc = ctx->opt.chain_levels > 0 ? ctx->opt.chain_levels : (ctx->opt.chain_levels < 0 ? 0 : 6);
+    const bool narrow = n <= 24 * (int64_t)std::min(Lf, Lb);
+    if (kc > 0 && narrow && 2 * n * (int64_t)es <= 160 * 1024) K = kc;
+  }
+  // entry counts per row and class
+  int4 *dcnt;
+  if ((rc = alloc(2 * n * sizeof(int4), (void **)&dcnt)) != LSQ_OK) return rc;
+  const unsigned rows_grid = (unsigned)((n * kWave + 255) / 256);
+  std::vector<int4> hcnt(2 * n);
+  int32_t maxlate = 0;
+  for (;;) {
+    for (int u = 0; u < 2; ++u) {
+      const int32_t *lv = u ? dlev_b : dlev_f;
+      if (dense)
+        k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, K, D, nullptr, nullptr, nullptr, lv,
+                                                       dcnt + u * n);
+      else
+        k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, K, D, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
+                                                        dcnt + u * n);
+    }
+    LSQ_HIP_CHECK(hipGetLastError());
+    LSQ_HIP_CHECK(hipMemcpyAsync(hcnt.data(), dcnt, 2 * n * sizeof(int4), hipMemcpyDeviceToHost, st));
+    LSQ_HIP_CHECK(hipStreamSynchronize(st));
+    maxlate = 0;
+    for (int64_t i = 0; i < 2 * n; ++i) maxlate = std::max(maxlate, hcnt[i].y);
+    // the chain holds at most 8 entries per lane
+    if (K == 1 || maxlate <= kChainLanes * 8) break;
+    K = 1;
+  }
+  const bool chain = K > 1;
+  int ec = 2;
+  while (kChainLanes * ec < maxlate) ec *= 2;
+  ctx->trsv_chain = chain;
+  ctx->trsv_ec = ec;
   constexpr int R = kMainR;
   bool too_big = false;
   int32_t maxnear = 0;
-  const size_t es = f32 ? sizeof(float) : sizeof(double);
   const void *val = f32 ? (const void *)ctx->Mf : (const void *)ctx->Md;
   int4 *dinfo;
   if ((rc = alloc(n * sizeof(int4), (void **)&dinfo)) != LSQ_OK) return rc;
@@ -771,7 +966,7 @@ int build_levels(lsq_ctx *ctx) {
         byl[fill[lev[i]]++] = (int32_t)i;
       }
     }
-    std::vector<int4> ta, tb, ft;
+    std::vector<int4> ta, tb, ft, cq;
     ta.reserve(n + (size_t)L * R);
     tb.reserve(n + (size_t)L * R);
     int64_t mpos = 0, fpos = 0, slot = 0;
@@ -782,6 +977,7 @@ int build_levels(lsq_ctx *ctx) {
         const int32_t nf = (c.z + kFarChunk - 1) / kFarChunk;
         info[i] = make_int4((int32_t)mpos, (int32_t)fpos, 0, 0);
         ta.push_back(make_int4(i, (int32_t)mpos, (int32_t)(mpos + c.x), c.y));
+        if (chain) cq.push_back(make_int4(i, (int32_t)(mpos + c.x), c.y, 0));
         tb.push_back(make_int4(l, 0, (int32_t)slot, nf));
         maxnear = std::max(maxnear, c.x);
         for (int32_t f = 0; f < nf; ++f) {
@@ -797,6 +993,7 @@ int build_levels(lsq_ctx *ctx) {
         ta.push_back(make_int4(-1, 0, 0, 0));
         tb.push_back(make_int4(0, 0, 0, 0));
       }
+      while (chain && cq.size() % kChainRows) cq.push_back(make_int4(-1, 0, 0, 0));
     }
     if (mpos >= INT32_MAX || fpos >= INT32_MAX || slot >= INT32_MAX) {
       too_big = true;
@@ -825,7 +1022,7 @@ int build_levels(lsq_ctx *ctx) {
     LSQ_HIP_CHECK(hipMemsetAsync(d.fval, 0, es + 16, st));
     const int32_t *rp = dense ? nullptr : ctx->Mrp, *ci = dense ? nullptr : ctx->Mci, *dgp = dense ? nullptr : ctx->Mdiag;
 #define LSQ_SCATTER(TT, DD)                                                                                     \
-  k_split_scatter<TT, DD><<<rows_grid, 256, 0, st>>>((int)n, upper, D, rp, ci, dgp, (const TT *)val, dl, dc, dinfo, \
+  k_split_scatter<TT, DD><<<rows_grid, 256, 0, st>>>((int)n, upper, K, D, rp, ci, dgp, (const TT *)val, dl, dc, dinfo, \
                                                      d.mci, (TT *)d.mval, d.fci, (TT *)d.fval)
     if (f32) {
       if (dense) LSQ_SCATTER(float, true);
@@ -837,6 +1034,27 @@ int build_levels(lsq_ctx *ctx) {
 #undef LSQ_SCATTER
     if (d.nft)
       k_far_probe<<<(unsigned)((d.nft * kWave + 255) / 256), 256, 0, st>>>((int)d.nft, d.ft, d.fci, dl);
+    if (chain) {
+      d.npass = (int64_t)cq.size() / kChainRows;
+      for (int r = 0; r < kChainRows; ++r) cq.push_back(make_int4(-1, 0, 0, 0));  // the empty pass
+      int4 *dcq;
+      if ((rc = alloc(cq.size() * sizeof(int4), (void **)&dcq)) != LSQ_OK) return rc;
+      const int64_t np1 = d.npass + 1;
+      if ((rc = alloc(np1 * kWave * sizeof(int32_t), (void **)&d.crow)) != LSQ_OK) return rc;
+      if ((rc = alloc(np1 * kWave * ec * sizeof(int32_t), (void **)&d.cj)) != LSQ_OK) return rc;
+      if ((rc = alloc(np1 * kWave * ec * es, (void **)&d.cv)) != LSQ_OK) return rc;
+      LSQ_HIP_CHECK(hipMemcpyAsync(dcq, cq.data(), cq.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+      const unsigned g = (unsigned)((np1 * kWave + 255) / 256);
+      if (f32)
+        k_chain_pack<float><<<g, 256, 0, st>>>((int)np1, ec, dcq, d.mci, (const float *)d.mval, d.crow, d.cj,
+                                              (float *)d.cv);
+      else
+        k_chain_pack<double><<<g, 256, 0, st>>>((int)np1, ec, dcq, d.mci, (const double *)d.mval, d.crow, d.cj,
+                                               (double *)d.cv);
+      LSQ_HIP_CHECK(hipGetLastError());
+      LSQ_HIP_CHECK(hipStreamSynchronize(st));
+      lsq_free_one(ctx, dcq);
+    }
     LSQ_HIP_CHECK(hipGetLastError());
     LSQ_HIP_CHECK(hipStreamSynchronize(st));  // info and the host vectors are reused
     return LSQ_OK;
@@ -903,11 +1121,11 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
     if (env_main && atoi(env_main) > 0) want = atoi(env_main);
     nmain = (int)std::max<int64_t>(1, std::min<int64_t>(want, c->ncu - helpers));
   }
-  // diagnostics: LSQ_TRSV_TRACE=<file> appends per-row shader-clock stamps of
-  // every triangular solve (header: n, batches, rows per batch, 0; per task
+  // diagnostics (built with LSQ_TRSV_STAMPS=1): LSQ_TRSV_TRACE=<file>
+  // appends per-row shader-clock stamps of every triangular solve (header: n, batches, rows per batch, 0; per task
   // slot 8 words: start, late-entry start, publish, level, late entries in,
   // row, 0, 0)
-  static const char *trace_path = getenv("LSQ_TRSV_TRACE");
+  static const char *trace_path = LSQ_TRSV_STAMPS ? getenv("LSQ_TRSV_TRACE") : nullptr;
   unsigned long long *trace = nullptr;
   const size_t slots = (size_t)d.nbatch * kMainR;
   if (trace_path) {
@@ -934,9 +1152,68 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
   }
 }
 
+template <typename T, int E, int EC>
+static void launch_trsv_chain(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
+  auto kern = k_trsv_chain<T, E, EC>;
+  const size_t lds = 2 * (size_t)c->n * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    attr_set = true;
+  }
+  const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
+  k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
+                                                                          (T *)c->farbuf);
+  constexpr int hwaves = kChainThreads / kWave;
+  const int helpers =
+      (int)std::min<int64_t>(std::min(kMaxChainHelpers, c->ncu - 1), (d.nft + hwaves - 1) / hwaves);
+  // diagnostics (built with LSQ_TRSV_STAMPS=1): LSQ_CHAIN_TRACE=<file>
+  // appends per-pass shader-clock stamps of every chain-mode solve (header:
+  // n, passes, 0, 1; per pass: start, base ready, x written, first row)
+  static const char *trace_path = LSQ_TRSV_STAMPS ? getenv("LSQ_CHAIN_TRACE") : nullptr;
+  unsigned long long *trace = nullptr;
+  if (trace_path && hipMalloc(&trace, 4 * d.npass * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
+  kern<<<1 + helpers, kChainThreads, lds, c->stream>>>(
+      (int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci, (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft, d.ft,
+      d.fci, (const T *)d.fval, (int)d.npass, d.crow, d.cj, (const T *)d.cv, x, (T *)c->farbuf, c->flags + 3, trace);
+  if (trace) {
+    std::vector<unsigned long long> h(4 * d.npass);
+    if (hipMemcpyAsync(h.data(), trace, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream) ==
+            hipSuccess &&
+        hipStreamSynchronize(c->stream) == hipSuccess) {
+      if (FILE *f = fopen(trace_path, "ab")) {
+        long long hdr[4] = {(long long)c->n, (long long)d.npass, 0, 1};
+        fwrite(hdr, sizeof(hdr), 1, f);
+        fwrite(h.data(), sizeof(unsigned long long), h.size(), f);
+        fclose(f);
+      }
+    }
+    (void)hipFree(trace);
+  }
+}
+
+template <typename T, int E>
+static void launch_trsv_chain_e(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
+  switch (c->trsv_ec) {
+    case 2: launch_trsv_chain<T, E, 2>(c, d, rhs, x); break;
+    case 4: launch_trsv_chain<T, E, 4>(c, d, rhs, x); break;
+    default: launch_trsv_chain<T, E, 8>(c, d, rhs, x); break;
+  }
+}
+
 template <typename T, bool UPPER>
 static void launch_trsv(lsq_ctx *c, const T *rhs, T *x) {
   const TriDev &d = UPPER ? c->tri_b : c->tri_f;
+  if (c->trsv_chain) {
+    switch (c->trsv_e) {
+      case 1: launch_trsv_chain_e<T, 1>(c, d, rhs, x); break;
+      case 2: launch_trsv_chain_e<T, 2>(c, d, rhs, x); break;
+      case 4: launch_trsv_chain_e<T, 4>(c, d, rhs, x); break;
+      default: launch_trsv_chain_e<T, 8>(c, d, rhs, x); break;
+    }
+    return;
+  }
   const bool lds = lds_fits<T>(c->n);
   switch (c->trsv_e) {
     case 1: lds ? launch_trsv_x<T, true, 1>(c, d, rhs, x) : launch_trsv_x<T, false, 1>(c, d, rhs, x); break;

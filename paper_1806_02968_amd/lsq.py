@@ -42,7 +42,7 @@ class Options(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int64), ("fixed_iters", C.c_int64),
                 ("max_replace", C.c_int32), ("inner_tol", C.c_double), ("max_inner", C.c_int64),
                 ("max_outer", C.c_int32), ("tie_eps", C.c_double), ("atap_algo", C.c_int32),
-                ("profile", C.c_int32), ("near_levels", C.c_int32)]
+                ("profile", C.c_int32), ("near_levels", C.c_int32), ("chain_levels", C.c_int32)]
 
 
 class KernelStats(C.Structure):
@@ -146,7 +146,7 @@ class Solver:
                  sweeps: int = 1, seed: int = 0, mode: str = "fp64", tol: float = 1e-10, max_iter: int = 0,
                  fixed_iters: int = -1, max_replace: int = 3, inner_tol: float = 1e-5, max_inner: int = 0,
                  max_outer: int = 30, tie_eps: float = 2.0 ** -44, atap_algo: int = 0, profile: bool = False,
-                 near_levels: int = 0):
+                 near_levels: int = 0, chain_levels: int = 0):
         import torch
         if b is None or not b.is_cuda or b.dtype != torch.float64 or not b.is_contiguous():
             raise ValueError("b must be a contiguous float64 CUDA tensor")
@@ -197,6 +197,7 @@ class Solver:
         opt.atap_algo = atap_algo
         opt.profile = 1 if profile else 0
         opt.near_levels = near_levels
+        opt.chain_levels = chain_levels
         self.m, self.n = int(mat.m), int(mat.n)
         self.mode = mode
         self.dtype = A.dtype if A is not None else values.dtype

@@ -339,3 +339,19 @@ def test_sparse_operator_kernels_agree(algo):
     xo, _ = o.solve(tol=1e-10)
     xt, _ = o.solve(tol=1e-13)
     assert rel(x.cpu().numpy(), xo) <= max(10 * rel(xo, xt), 1e-9)
+
+
+@pytest.mark.parametrize("name,chain", [("sparse", -1), ("sparse", 3), ("sparse", 12), ("udv", -1), ("udv", 0)])
+def test_triangular_solve_modes(name, chain):
+    """P r with the chain wave off and with several chain depths (sparse M with
+    narrow levels; dense M, one row per level) against the oracle."""
+    import torch
+    print("\n[trsv mode] %s chain_levels=%d" % (name, chain), flush=True)
+    p = FAMILIES[name]()
+    t = SWEEPS[name]
+    s, _ = make_solver(p, C_=4.0, sweeps=t, seed=0, chain_levels=chain)
+    _, _, idx, _ = s.setup_arrays(want_w=False)
+    o = oracle.Oracle(p, C_=4.0, sweeps=t, seed=0, samples=idx)
+    r = np.random.default_rng(7).standard_normal(s.n)
+    z = s.apply_P(torch.from_numpy(r).cuda()).cpu().numpy()
+    assert rel(z, o.apply_P(r)) <= 1e-10

@@ -25,9 +25,11 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}  # dense matrix-core pea
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (calibrated on a 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE
-# x 1.0), per workload and kernel class; the profile summary in profiles/
-# gives the commands. Measured on the triangular-solve code of this revision.
-MEASURED_TRAFFIC = {("sparse", "trsv"): 57.89e6}
+# x 1.0), per workload and kernel; the profile summary in profiles/ gives the
+# commands. Only figures taken on the kernel code of this revision are listed.
+MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 63.52e6}
+# triangular-solve kernel by lsq_info.trsv_mode
+TRSV_KERNEL = {0: "k_trsv (x in LDS)", 1: "k_trsv_chain", 2: "k_trsv (x in global memory)"}
 
 WORKLOADS = {
     "sparse": "sparse CSR 1000000x10000, 10 nnz/row at uniform distinct columns, N(0,1) values, "
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--mode", default="both", choices=["fp64", "fp32_refine", "both"],
                     help="both: FP64 (the reported value) and FP32 inner PCG + FP64 refinement, timed alike")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cg-baseline", action="store_true",
+                    help="skip the unpreconditioned CG run (sweeps = 0) reported beside the main one")
     ap.add_argument("--atap-algo", type=int, default=0)
     ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
     ap.add_argument("--chain-levels", type=int, default=0,
@@ -96,14 +100,15 @@ def main():
                    col_idx=torch.from_numpy(p.col_idx).cuda())
     torch.cuda.synchronize()
 
-    def step(mode, profile):
+    def step(mode, profile, sweeps=None):
+        sweeps = cfg["sweeps"] if sweeps is None else sweeps
         if p.fmt == "dense":
-            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
+            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=sweeps, seed=0, mode=mode, profile=profile,
                        atap_algo=args.atap_algo, near_levels=args.near_levels,
                        chain_levels=args.chain_levels, max_iter=args.max_iter)
         else:
             s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
-                       b=b, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode=mode, profile=profile,
+                       b=b, C_=cfg["C"], sweeps=sweeps, seed=0, mode=mode, profile=profile,
                        atap_algo=args.atap_algo, near_levels=args.near_levels,
                        chain_levels=args.chain_levels, max_iter=args.max_iter)
         x, info = s.solve()
@@ -111,17 +116,17 @@ def main():
         s.close()
         return x, info, ks
 
-    def run(mode):
+    def run(mode, sweeps=None):
         """W untimed steps, then K timed steps bracketed by synchronizations."""
         for w in range(args.warmup):
-            step(mode, False)
+            step(mode, False, sweeps)
             print("[bench] %s warm-up %d/%d done" % (mode, w + 1, args.warmup), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         infos, kstats = [], []
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for k in range(args.steps):
-            x, info, ks = step(mode, True)
+            x, info, ks = step(mode, True, sweeps)
             infos.append(info)
             kstats.append(ks)
             print("[bench] %s step %d/%d: %d iterations" % (mode, k + 1, args.steps, info["iters"]), file=sys.stderr,
@@ -156,10 +161,11 @@ def main():
     per_launch_bytes = dv["bytes"] / dv["launches"]
     avg_s = dv["ms"] / dv["launches"] * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9
-    roofline = {"kernel": {"trsv": "k_trsv", "sgs_rhs": "k_sgs_rhs", "atap": "A^T(Ap) kernels",
-                           "vec": "vector kernels"}[dom],
+    kname = {"trsv": TRSV_KERNEL[int(infos[-1]["trsv_mode"])], "sgs_rhs": "k_sgs_rhs", "atap": "A^T(Ap) kernels",
+             "vec": "vector kernels"}[dom]
+    roofline = {"kernel": kname,
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.config, dom)),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.config, kname)),
                 "bytes_per_launch": per_launch_bytes, "avg_launch_us": avg_s * 1e6}
     at = classes.get("atap")
     atap_gbs = (at["bytes"] / at["ms"] * 1e-6) if at and at["ms"] > 0 else None
@@ -187,6 +193,8 @@ def main():
         "levels": int(last["levels_fwd"]),
         "atap_gbs": atap_gbs,
         "atap_frac": (atap_gbs / HBM_PEAK_GBS) if atap_gbs else None,
+        "atap_algo": int(last["atap_algo"]),
+        "trsv_kernel": TRSV_KERNEL[int(last["trsv_mode"])],
         "kernels": kernels,
         "roofline": roofline,
     }
@@ -210,6 +218,17 @@ def main():
             tf = rg["bytes"] / (rg["ms"] * 1e-3) / 1e12
             out[m]["gram"] = {"avg_ms": rg["ms"] / rg["launches"], "tflops": tf,
                               "peak_tflops": MFMA_PEAK_TFLOPS[m], "frac": tf / MFMA_PEAK_TFLOPS[m]}
+
+    if not args.no_cg_baseline:
+        # the paper's comparison column: CG on the normalised normal equations
+        # (no Gauss-Seidel sweeps, P = I), same library, same timing
+        r = run("fp64", sweeps=0)
+        li = r["infos"][-1]
+        out["cg_baseline"] = {"sweeps": 0, "ms_per_step": r["ms_per_step"],
+                              "setup_ms": float(np.mean([i["setup_ms"] for i in r["infos"]])),
+                              "solve_ms": float(np.mean([i["solve_ms"] for i in r["infos"]])),
+                              "iters": int(li["iters"]), "relres_true": float(li["relres_true"]),
+                              "converged": int(li["converged"])}
 
     if not args.no_cpu_baseline:
         import oracle

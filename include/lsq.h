@@ -84,7 +84,8 @@ typedef struct {
   int32_t max_outer;   /* FP32_REFINE: refinement steps cap (30)             */
   double tie_eps;      /* CDF-boundary tie band for reporting draws (2^-44)  */
   int32_t atap_algo;   /* A^T(Ap) kernel: 0 auto; sparse A: 1 global atomics,
-                          2 workgroup partial sums in LDS; dense A: 1 one
+                          2 workgroup partial sums in LDS, 3 a row pass then a
+                          pass over a column-major copy of A; dense A: 1 one
                           wave per row, 2 row batches staged in LDS, 3 one
                           wave per row with 16-byte loads                     */
   int32_t profile;     /* nonzero: time every hot-kernel launch with HIP
@@ -121,6 +122,12 @@ typedef struct {
   double solve_ms;      /* last lsq_solve / lsq_backward wall time            */
   int32_t converged;    /* 1 if relres_true <= tol                            */
   int32_t status;       /* return code of the last call                       */
+  int32_t trsv_mode;    /* triangular solves: 0 one main workgroup with x in
+                           LDS, 1 chain mode, 2 main workgroups with x in
+                           global memory                                      */
+  int32_t atap_algo;    /* sparse A: the A^T(Ap) kernel in use (values of
+                           lsq_options.atap_algo); dense A: the option as
+                           given (0: chosen per call by the vector length)    */
 } lsq_info;
 
 typedef struct lsq_ctx lsq_ctx;

@@ -943,6 +943,7 @@ int build_levels(lsq_ctx *ctx) {
   while (kChainLanes * ec < maxlate) ec *= 2;
   ctx->trsv_chain = chain;
   ctx->trsv_ec = ec;
+  ctx->info.trsv_mode = chain ? 1 : (n * (int64_t)es <= 150 * 1024 ? 0 : 2);
   constexpr int R = kMainR;
   bool too_big = false;
   int32_t maxnear = 0;

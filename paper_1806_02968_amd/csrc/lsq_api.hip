@@ -486,6 +486,7 @@ static int setup_impl(lsq_ctx *ctx) {
   ctx->info.nnz_M = ctx->nnzM;
   ctx->info.levels_fwd = ctx->nlev_f;
   ctx->info.levels_bwd = ctx->nlev_b;
+  ctx->info.atap_algo = ctx->fmt == LSQ_CSR ? ctx->atap_algo : ctx->opt.atap_algo;
   ctx->info.ties = hflags[2];
   ctx->info.diag_fixes = hflags[1];
   ctx->info.W = ctx->W;

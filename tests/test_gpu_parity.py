@@ -355,3 +355,60 @@ def test_triangular_solve_modes(name, chain):
     r = np.random.default_rng(7).standard_normal(s.n)
     z = s.apply_P(torch.from_numpy(r).cuda()).cpu().numpy()
     assert rel(z, o.apply_P(r)) <= 1e-10
+
+
+def test_backward_finite_differences_full_graph():
+    """Adjoint gradients of L = |x - x_t|^2 / 2 on the 2,000,000 x 99,999 graph
+    problem (5 sweeps) against central differences along 8 random directions
+    in b and 8 in A's stored values, to 1e-6 relative.
+
+    The +/- solves run a fixed iteration count (a fixed count keeps the
+    solver's remaining error a smooth function of the data): the count that
+    brings the unperturbed solve to 1e-12 for b, twice that for A. L is linear
+    -quadratic in b, so one difference is exact up to that error; in A the
+    central difference carries an h^2 term (measured: it grows 16x from h to
+    4h), removed by Richardson extrapolation from steps h and 4h. The error
+    is compared with max(|<g, d>|, |g|): |g| is the typical size of <g, d>
+    over Gaussian directions d, so a direction nearly orthogonal to g does not
+    turn an absolute error into a large relative one."""
+    import torch
+    print("\n[FD] graph full size", flush=True)
+    p = make_config("graph", scale="full")[0]
+    dev = device_problem(p)
+    x_t = torch.from_numpy(np.random.default_rng(21).standard_normal(p.n)).cuda()
+
+    def solver(values, b, **kw):
+        return make_solver(p, dev=dict(dev, values=values, b=b), C_=4.0, sweeps=5, seed=0, **kw)[0]
+
+    s = solver(dev["values"], dev["b"], tol=1e-12)
+    x, info = s.solve()
+    assert info["relres_true"] <= 1e-12
+    k = int(info["iters"])
+    lam, gb, gA, _ = s.backward(x, x - x_t)
+
+    def fd(plus, minus, h, iters):
+        # L(x+) - L(x-) = <x+ - x-, (x+ + x-)/2 - x_t>, free of the rounding
+        # of the two large sums
+        xp = solver(*plus, fixed_iters=iters).solve()[0]
+        xm = solver(*minus, fixed_iters=iters).solve()[0]
+        return float(torch.dot(xp - xm, 0.5 * (xp + xm) - x_t)) / (2 * h)
+
+    rng = np.random.default_rng(22)
+    vals, b = dev["values"], dev["b"]
+    nb, nA = float(torch.linalg.norm(gb)), float(torch.linalg.norm(gA))
+    for t in range(8):
+        d = torch.from_numpy(rng.standard_normal(p.m)).cuda()
+        h = 1e-3 * float(torch.linalg.norm(b) / torch.linalg.norm(d))
+        q = fd((vals, b + h * d), (vals, b - h * d), h, k)
+        an = float(torch.dot(gb, d))
+        print("[FD] b dir %d: fd %.9e adjoint %.9e" % (t, q, an), flush=True)
+        assert abs(q - an) <= 1e-6 * max(abs(an), nb)
+    for t in range(8):
+        d = torch.from_numpy(rng.standard_normal(p.nnz)).cuda()
+        h = 1e-6 * float(torch.linalg.norm(vals) / torch.linalg.norm(d))
+        q1 = fd((vals + h * d, b), (vals - h * d, b), h, 2 * k)
+        q4 = fd((vals + 4 * h * d, b), (vals - 4 * h * d, b), 4 * h, 2 * k)
+        q = (16 * q1 - q4) / 15
+        an = float(torch.dot(gA, d))
+        print("[FD] A dir %d: fd(h) %.9e fd(4h) %.9e extrapolated %.9e adjoint %.9e" % (t, q1, q4, q, an), flush=True)
+        assert abs(q - an) <= 1e-6 * max(abs(an), nA)

@@ -87,7 +87,10 @@ typedef struct {
                           2 workgroup partial sums in LDS, 3 a row pass then a
                           pass over a column-major copy of A; dense A: 1 one
                           wave per row, 2 row batches staged in LDS, 3 one
-                          wave per row with 16-byte loads                     */
+                          wave per row with 16-byte loads, 4 column groups
+                          owned by threads, row batches in registers (n a
+                          multiple of 4 / 2 for float32 / float64 storage,
+                          n <= 2048 / 1024, rows 16-byte aligned)            */
   int32_t profile;     /* nonzero: time every hot-kernel launch with HIP
                           events on the context's stream (lsq_get_kernel_stats) */
   int32_t near_levels; /* triangular solves: entries reading rows at most this

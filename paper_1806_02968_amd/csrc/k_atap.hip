@@ -270,6 +270,94 @@ __global__ __launch_bounds__(kAtThreads) void k_atap_dense_lds(int64_t m, int n,
   }
 }
 
+// Dense A, column-owned row batches: thread t of the block owns the V-element
+// groups t, t + 256, ... of every row (16-byte loads, consecutive threads on
+// consecutive groups), so A goes from HBM straight to registers and each
+// thread keeps its columns' output sums in registers. A batch of RB rows is
+// requested while the previous batch is reduced: each thread forms its part
+// of every row dot, the parts are summed over the wave (DPP) and over the
+// four waves (LDS, one barrier per batch, fixed order), and each thread adds
+// t_r a_r for its columns. Needs n % V == 0 and rows aligned to 16 bytes.
+template <typename TA, typename CT, int NC, int V, int RB, bool HAS_B>
+__global__ __launch_bounds__(kAtThreads) void k_atap_dense_cols(int64_t m, int n, int64_t ld,
+                                                                const TA *__restrict__ A, const CT *__restrict__ u,
+                                                                const double *__restrict__ b, CT *__restrict__ part,
+                                                                int64_t rows_per_blk) {
+  __shared__ CT red[2][kAtWaves][RB];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int ng = n / V;  // V-element groups per row
+  int gi[NC];            // this thread's groups, clamped in range
+  bool gon[NC];
+  CT uv[NC][V], acc[NC][V];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int g = threadIdx.x + kAtThreads * c;
+    gon[c] = g < ng;
+    gi[c] = gon[c] ? g : ng - 1;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      uv[c][e] = gon[c] ? u[gi[c] * V + e] : (CT)0;
+      acc[c][e] = 0;
+    }
+  }
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  const int nbatch = (int)((r1 - r0 + RB - 1) / RB);
+  TA a[2][RB][NC][V];
+  auto load = [&](int k, TA (&dst)[RB][NC][V]) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int64_t row = r0 + (int64_t)k * RB + r;
+      row = row < r1 ? row : r1 - 1;
+      const TA *p = A + row * ld;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) vload<TA, V>(p + gi[c] * V, dst[r][c]);
+    }
+  };
+  auto consume = [&](int k, const TA (&src)[RB][NC][V]) {
+    CT d[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      CT s = 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < V; ++e) s += gon[c] ? (CT)src[r][c][e] * uv[c][e] : (CT)0;
+      d[r] = dpp_group_sum<kWave>(s);
+    }
+    if (lane == dpp_sum_lane<kWave>())
+#pragma unroll
+      for (int r = 0; r < RB; ++r) red[k & 1][wave][r] = d[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int64_t row = r0 + (int64_t)k * RB + r;
+      CT t = 0;
+#pragma unroll
+      for (int w = 0; w < kAtWaves; ++w) t += red[k & 1][w][r];
+      if (HAS_B) t = (CT)b[row < r1 ? row : r1 - 1] - t;
+      t = row < r1 ? t : (CT)0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[c][e] += t * (CT)src[r][c][e];
+    }
+  };
+  if (nbatch > 0) load(0, a[0]);
+  for (int k = 0; k < nbatch; k += 2) {
+    if (k + 1 < nbatch) load(k + 1, a[1]);
+    consume(k, a[0]);
+    if (k + 1 >= nbatch) break;
+    if (k + 2 < nbatch) load(k + 2, a[0]);
+    consume(k + 1, a[1]);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (gon[c])
+#pragma unroll
+      for (int e = 0; e < V; ++e) part[blockIdx.x * (int64_t)n + gi[c] * V + e] = acc[c][e];
+}
+
 // first level of the partial-row reduction: blockIdx.y sums rows
 // [y*seg, (y+1)*seg) of part into row y of out (fixed order)
 template <typename CT>
@@ -508,12 +596,34 @@ static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, 
   const int64_t R = std::min<int64_t>(64, (lds_budget - (n + 2) * (int64_t)sizeof(CT)) / (n * (int64_t)sizeof(TA)));
   const bool lds_ok = n <= 256 * 16 && R >= 4;
   int algo = c->opt.atap_algo;
+  // column-owned batches: two groups of V columns per thread at most
+  const bool cols_ok = vec_ok && n <= 2 * kAtThreads * V;
+  if (algo == 4 && !cols_ok) algo = 0;
   if (algo == 0 || (algo == 3 && !vec_ok) || (algo == 2 && !lds_ok)) {
     // registers hold u, the output row and two rows of A per lane; the
     // LDS-staged form takes over when that does not fit (float storage,
     // float64 arithmetic, long rows)
     const int64_t per_lane = (n + kWave - 1) / kWave * (2 * sizeof(TA) + 2 * sizeof(CT)) / 4;
     algo = per_lane <= 128 ? (vec_ok ? 3 : 1) : (lds_ok ? 2 : 1);
+    // column-owned batches for long float32 rows (2 million x 2000: 5.9 TB/s
+    // against 3.1 for the LDS form with float64 arithmetic, 6.0 against 5.3
+    // for one wave per row in float32) and for rows too long for registers
+    if (cols_ok && n > 512 && (sizeof(TA) == 4 || per_lane > 128)) algo = 4;
+  }
+  if (algo == 4) {
+    const int nblk = dense_blocks(m);
+    const int64_t rpb = (m + nblk - 1) / nblk;
+    // rows per batch: two batches of RB rows in registers (8 KB per wave each)
+    if (n <= kAtThreads * V)
+      k_atap_dense_cols<TA, CT, 1, V, 8, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    else
+      k_atap_dense_cols<TA, CT, 2, V, 4, HAS_B><<<nblk, kAtThreads, 0, st>>>(m, nb, c->ld, A, u, b, part, rpb);
+    const int nseg = (nblk + seg - 1) / seg;
+    CT *part2 = part + (int64_t)nblk * n;
+    const int64_t fb = (n + 255) / 256;
+    k_part_reduce<CT><<<dim3((unsigned)fb, (unsigned)nseg), 256, 0, st>>>(n, part, nblk, seg, part2);
+    k_atap_finish<CT><<<(unsigned)fb, 256, 0, st>>>(n, part2, nseg, s_out, q);
+    return;
   }
   if (algo == 3) {
     const int nblk = dense_blocks(m);

@@ -647,55 +647,92 @@ __device__ __forceinline__ void tri_range(bool upper, int i, const int32_t *__re
   *b = upper ? rp[i + 1] : dg[i];
 }
 
-// Levels of the rows of one triangle of a CSR M (block 0: lower part in
-// natural order, block 1: upper part in reverse order). Wave w takes the
-// rows w, w+16, ... of the solve order; a row's level is one more than the
-// largest level among the rows it reads, waited for in LDS (or global memory
-// when n ints do not fit) where levels start as -1. Rows read only rows
-// earlier in the solve order, so the earliest unfinished row can always
-// finish.
+// Levels of the rows of one triangle of a CSR M (blocks [0, nb): lower part
+// in natural order, blocks [nb, 2 nb): upper part in reverse order; nb = 1
+// when the levels are kept in LDS). Wave w of a triangle's blocks takes the
+// rows w, w + W, ... of the solve order (W waves in all); a row's level is one
+// more than the largest level among the rows it reads, waited for in LDS (or
+// global memory when n ints do not fit) where levels start as -1. Rows read
+// only rows earlier in the solve order, so the earliest unfinished row can
+// always finish (all blocks are resident). A wave requests the next row's
+// column indices before it waits for the current row's levels; all reads are
+// issued from clamped indices before any is waited for.
 template <bool LDSL>
-__global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, int nb, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          const int32_t *__restrict__ dg, int32_t *__restrict__ lev_f,
                                                          int32_t *__restrict__ lev_b, int32_t *__restrict__ err) {
   constexpr int E = 8;
   extern __shared__ __align__(16) unsigned char smem[];
-  const bool upper = blockIdx.x == 1;
+  const bool upper = (int)blockIdx.x >= nb;
   int32_t *out = upper ? lev_b : lev_f;
   int32_t *lv = LDSL ? (int32_t *)smem : out;
   constexpr int scope = LDSL ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
   if (LDSL)
     for (int i = threadIdx.x; i < n; i += kTrsvThreads) lv[i] = -1;
   __syncthreads();  // the global array starts at -1 (set before the launch)
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  auto level_of = [&](int j, int &spins) -> int {  // waits for row j's level
-    int v = __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope);
-    while (v < 0) {
-      __builtin_amdgcn_s_sleep(1);
-      if (give_up(spins, err)) return 0;
-      v = __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope);
-    }
-    return v;
+  const int lane = threadIdx.x % kWave;
+  const int gw = (int)(blockIdx.x % nb) * kTrsvWaves + threadIdx.x / kWave, W = nb * kTrsvWaves;
+  auto ld_level = [&](int j) -> int { return __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope); };
+  struct Row {
+    int i, a, b;
+    int j[E];
   };
-  for (int q = wave; q < n; q += kTrsvWaves) {
-    const int i = upper ? n - 1 - q : q;
-    int a, b;
-    tri_range(upper, i, rp, dg, &a, &b);
+  // row bounds and the first E column indices per lane (clamped reads)
+  auto fetch = [&](int q, Row &r) {
+    const int qq = q < n ? q : n - 1;
+    r.i = upper ? n - 1 - qq : qq;
+    tri_range(upper, r.i, rp, dg, &r.a, &r.b);
+    if (q >= n) r.b = r.a;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = r.a + lane + kWave * e;
+      r.j[e] = ci[k < r.b ? k : (r.b > r.a ? r.a : 0)];
+    }
+  };
+  auto level = [&](Row &r) -> int {
     int mx = -1, spins = 0;
-    for (int k0 = a; k0 < b; k0 += kWave * E) {
-      int j[E];
+    for (int k0 = r.a; k0 < r.b; k0 += kWave * E) {
+      if (k0 != r.a) {  // rows longer than E per lane (rare): the next chunk
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int k = k0 + lane + kWave * e;
+          r.j[e] = ci[k < r.b ? k : k0];
+        }
+      }
+      int v[E], pend = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = ld_level(r.j[e]);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int k = k0 + lane + kWave * e;
-        j[e] = k < b ? ci[k] : -1;
+        const bool on = k0 + lane + kWave * e < r.b;
+        pend |= on && v[e] < 0 ? 1 << e : 0;
+        mx = on && v[e] > mx ? v[e] : mx;
       }
+      while (pend) {  // levels not yet known: wait for them
+        __builtin_amdgcn_s_sleep(1);
+        if (give_up(spins, err)) break;
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (j[e] >= 0) mx = max(mx, level_of(j[e], spins));
+        for (int e = 0; e < E; ++e) {
+          if (!((pend >> e) & 1)) continue;
+          const int u = ld_level(r.j[e]);
+          if (u >= 0) {
+            mx = u > mx ? u : mx;
+            pend &= ~(1 << e);
+          }
+        }
+      }
     }
+    return mx;
+  };
+  Row cur, nxt;
+  fetch(gw, cur);
+  for (int q = gw; q < n; q += W) {
+    fetch(q + W, nxt);
+    int mx = level(cur);
     mx = dpp_wave_max(mx);
-    if (lane == kWave - 1) __hip_atomic_store(lv + i, mx + 1, __ATOMIC_RELAXED, scope);
+    if (lane == kWave - 1) __hip_atomic_store(lv + cur.i, mx + 1, __ATOMIC_RELAXED, scope);
+    cur = nxt;
   }
   if (LDSL) {
     __syncthreads();
@@ -881,11 +918,13 @@ int build_levels(lsq_ctx *ctx) {
         (void)hipGetLastError();
         attr = true;
       }
-      k_levels<true><<<2, kTrsvThreads, n * 4, st>>>((int)n, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
+      k_levels<true><<<2, kTrsvThreads, n * 4, st>>>((int)n, 1, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
                                                      ctx->flags + 3);
     } else {
       launch_fill_i32(dlev, 2 * n, -1, st);
-      k_levels<false><<<2, kTrsvThreads, 0, st>>>((int)n, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
+      // levels in global memory: many workgroups per triangle, all resident
+      const int nb = std::max(1, std::min(64, ctx->ncu / 2));
+      k_levels<false><<<2 * nb, kTrsvThreads, 0, st>>>((int)n, nb, ctx->Mrp, ctx->Mci, ctx->Mdiag, dlev_f, dlev_b,
                                                   ctx->flags + 3);
     }
     LSQ_HIP_CHECK(hipGetLastError());

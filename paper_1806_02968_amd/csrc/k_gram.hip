@@ -284,32 +284,51 @@ __device__ void bitonic_block(uint64_t *k, double *v, int N) {
 // reduce a sorted row (P entries at k, v) by column, insert/guard the
 // diagonal, and write cols/vals to (oc, ov); returns the count in *cnt_out.
 // heads: LDS int array of >= P + 1 entries. Executed by the whole block.
+// NT: the block's threads.
+template <int NT>
 __device__ void reduce_sorted_row(const uint64_t *k, const double *v, int64_t P, int32_t j, int32_t *oc,
                                   double *ov, int *heads, int64_t *cnt_out, int32_t *flags) {
-  __shared__ int nh, ins, has_diag;
-  // head flags and their exclusive positions (sequential scan by thread 0;
-  // rows are short)
-  for (int64_t t = threadIdx.x; t < P; t += blockDim.x) {
-    uint32_t c = (uint32_t)(k[t] >> 32);
-    heads[t] = (t == 0 || (uint32_t)(k[t - 1] >> 32) != c) ? 1 : 0;
+  __shared__ int wcnt[NT / kWave], wbelow[NT / kWave], wdiag[NT / kWave];
+  // head flags (first entry of each column) and their exclusive positions:
+  // thread t scans a contiguous chunk, the chunk counts are scanned over the
+  // block in thread order
+  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, nw = NT / kWave;
+  const int chunk = (int)((P + NT - 1) / NT);
+  const int t0 = (int)min<int64_t>(P, (int64_t)tid * chunk), t1 = (int)min<int64_t>(P, (int64_t)t0 + chunk);
+  auto col = [&](int t) -> uint32_t { return (uint32_t)(k[t] >> 32); };
+  int cnt = 0, below = 0, hd = 0;
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t c = col(t);
+    const bool h = t == 0 || col(t - 1) != c;
+    cnt += h;
+    below += h && (int32_t)c < j;
+    hd |= h && (int32_t)c == j;
+  }
+  int incl = cnt;  // inclusive scan over the wave
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int wb = wave_sum(below);
+  const bool wd = __ballot(hd != 0) != 0;
+  if (lane == kWave - 1) {
+    wcnt[wid] = incl;
+    wbelow[wid] = wb;
+    wdiag[wid] = wd;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0, ip = -1, hd = 0;
-    for (int64_t t = 0; t < P; ++t) {
-      int h = heads[t];
-      if (h) {
-        uint32_t c = (uint32_t)(k[t] >> 32);
-        if ((int32_t)c == j) hd = 1;
-        if (ip < 0 && (int32_t)c >= j) ip = run;
-      }
-      heads[t] = h ? run : -1;
-      run += h;
-    }
-    if (ip < 0) ip = run;
-    nh = run;
-    ins = ip;
-    has_diag = hd;
+  int base = 0, nh = 0, ins = 0, has_diag = 0;
+  for (int w = 0; w < nw; ++w) {
+    base += w < wid ? wcnt[w] : 0;
+    nh += wcnt[w];
+    ins += wbelow[w];
+    has_diag |= wdiag[w];
+  }
+  int run = base + incl - cnt;
+  for (int t = t0; t < t1; ++t) {
+    const bool h = t == 0 || col(t - 1) != col(t);
+    heads[t] = h ? run++ : -1;
   }
   __syncthreads();
   const int shift_from = has_diag ? 0x7fffffff : ins;
@@ -365,7 +384,7 @@ __global__ __launch_bounds__(kSortT) void k_row_small(int64_t n, const int64_t *
     bitonic_block(sk, sv, N);
     // output positions are offset by the row's own index so that a row
     // with P products can hold P + 1 entries (the inserted diagonal)
-    reduce_sorted_row(sk, sv, P, (int32_t)j, ocol + S + j, oval + S + j, heads, &ucount[j], flags);
+    reduce_sorted_row<kSortT>(sk, sv, P, (int32_t)j, ocol + S + j, oval + S + j, heads, &ucount[j], flags);
   }
 }
 
@@ -384,7 +403,7 @@ __global__ __launch_bounds__(1024) void k_row_big(int64_t j, const int64_t *__re
   }
   __syncthreads();
   bitonic_block(sk, sv, N);
-  reduce_sorted_row(sk, sv, P, (int32_t)j, ocol + S + j, oval + S + j, heads, &ucount[j], flags);
+  reduce_sorted_row<1024>(sk, sv, P, (int32_t)j, ocol + S + j, oval + S + j, heads, &ucount[j], flags);
 }
 
 __global__ void k_gather_M(int64_t n, const int64_t *__restrict__ cptr, const int64_t *__restrict__ poff,

@@ -100,7 +100,9 @@ typedef struct {
   int32_t chain_levels; /* triangular solves: when x and the rows' partial sums
                           fit in LDS and levels hold few rows, one wave sums
                           the entries reading rows at most this many levels
-                          below (0: 6; -1: off; at most 64)                   */
+                          below (0: automatic, the most levels from 6 down to
+                          2 that keep at most 8 such entries per row; -1: off;
+                          at most 64)                                        */
 } lsq_options;
 
 /* Fills *opt with the defaults above. */

@@ -266,7 +266,7 @@ extern "C" void lsq_default_options(lsq_options *o) {
   o->tie_eps = 0x1.0p-44;
   o->atap_algo = 0;
   o->near_levels = 48;
-  o->chain_levels = 6;
+  o->chain_levels = 0;
 }
 
 extern "C" const char *lsq_strerror(int code) {
@@ -514,7 +514,6 @@ extern "C" int lsq_setup(const lsq_matrix *A, const double *b, double C, int32_t
   if (o.max_outer <= 0) o.max_outer = 30;
   if (o.near_levels <= 0) o.near_levels = 48;
   if (o.near_levels > 1024) return LSQ_EINVAL;
-  if (o.chain_levels == 0) o.chain_levels = 6;
   if (o.chain_levels > 64 || o.chain_levels < -1) return LSQ_EINVAL;
 
   lsq_ctx *ctx = new lsq_ctx();

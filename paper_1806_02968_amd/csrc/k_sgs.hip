@@ -55,19 +55,19 @@ constexpr int kFarE = 8, kFarChunk = kWave * kFarE;               // helpers: on
 // up to kLateLanes lanes per row.
 constexpr int kLateLevels = 1, kLateLanes = 4;
 constexpr int kMaxHelpers = 32;
-// Chain mode (x and the rows' bases both fit in LDS): one wave of a
-// kChainThreads-thread main block takes the entries of the kChainLevels
-// levels below each row itself, kChainRows rows of a level per pass with
-// kChainLanes lanes per row; the block's other waves compute the bases.
 // clock stamps of the triangular solves, a diagnostic build only (reading
 // the clock slows the solve even when no stamp is written)
 #ifndef LSQ_TRSV_STAMPS
 #define LSQ_TRSV_STAMPS 0
 #endif
-#ifndef LSQ_CHAIN_THREADS
-#define LSQ_CHAIN_THREADS 512
-#endif
-constexpr int kChainThreads = LSQ_CHAIN_THREADS, kChainLanes = 4, kChainRows = kWave / kChainLanes;
+// Chain mode (x and the rows' bases both fit in LDS): one wave of the main
+// workgroup takes the entries of the few levels below each row itself,
+// kChainRows rows of a level per pass with kChainLanes lanes per row; the
+// workgroup's other waves compute the bases. 1024 threads (15 base waves)
+// while the registers allow it (up to 4 chain entries and 4 near entries per
+// lane), else 512 (1M x 10k sparse: 396 against 411 us per solve).
+constexpr int kChainLanes = 4, kChainRows = kWave / kChainLanes;
+constexpr int chain_threads(int e, int ec) { return ec <= 4 && e <= 4 ? 1024 : 512; }
 constexpr int kMaxChainHelpers = 64;
 constexpr int kSpinLimit = 1 << 22;
 
@@ -465,9 +465,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int n, const int4 *__rest
 // level (level order), kChainLanes lanes per row: crow[p][lane] is the row of
 // the lane's group (-1: none), cj/cv[p][e][lane] entry q + 4e (q = lane % 4)
 // of the row's chain part (column -1: none; pass npass is empty), i.e. the
-// entries reading rows at
-// most kChainLevels levels below. Those rows were all written by this wave
-// in earlier passes, and LDS accesses of one wave complete in order, so
+// entries reading rows at most chain_levels levels below. Those rows were
+// all written by this wave in earlier passes, and LDS accesses of one wave
+// complete in order, so
 // their x values are read without polling. x_i = base_i - (chain sum), with
 // base_i (r_i / M_ii minus the near and far sums) published in LDS by the
 // block's other waves, normally well before the chain gets there.
@@ -560,7 +560,7 @@ __device__ __forceinline__ void trsv_chain(int npass, const int32_t *__restrict_
 // Chain mode: block 0 holds x and the bases in LDS; its wave 0 is the chain,
 // its other waves compute the bases; blocks 1.. are helpers.
 template <typename T, int E, int EC>
-__global__ __launch_bounds__(kChainThreads) void k_trsv_chain(
+__global__ __launch_bounds__(chain_threads(E, EC)) void k_trsv_chain(
     int n, const int4 *__restrict__ ta, const int4 *__restrict__ tb, int nbatch, const int32_t *__restrict__ mci,
     const T *__restrict__ mval, const T *__restrict__ diag, const T *__restrict__ rhs, int nft,
     const int4 *__restrict__ ft, const int32_t *__restrict__ fci, const T *__restrict__ fval, int npass,
@@ -570,14 +570,15 @@ __global__ __launch_bounds__(kChainThreads) void k_trsv_chain(
   extern __shared__ __align__(16) unsigned char smem[];
   if (blockIdx.x == 0) {
     T *xs = (T *)smem;
-    for (int i = threadIdx.x; i < 2 * n; i += kChainThreads) ((U *)xs)[i] = Bits<T>::kSent;
+    constexpr int NT = chain_threads(E, EC);
+    for (int i = threadIdx.x; i < 2 * n; i += NT) ((U *)xs)[i] = Bits<T>::kSent;
     __syncthreads();
     if (threadIdx.x < kWave)
       trsv_chain<T, EC>(npass, crow, cj, cv, xs, xs + n, x, err, trace);
     else
-      trsv_main<T, true, E, true, kChainThreads>(n, 1, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, nullptr);
+      trsv_main<T, true, E, true, NT>(n, 1, ta, tb, nbatch, mci, mval, diag, rhs, x, far, err, nullptr);
   } else {
-    trsv_helper<T, kChainThreads>(1, nft, ft, fci, fval, x, far, err);
+    trsv_helper<T, chain_threads(E, EC)>(1, nft, ft, fci, fval, x, far, err);
   }
 }
 
@@ -1214,7 +1215,7 @@ static void launch_trsv_chain(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
   const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
   k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
                                                                           (T *)c->farbuf);
-  constexpr int hwaves = kChainThreads / kWave;
+  constexpr int hwaves = chain_threads(E, EC) / kWave;
   const int helpers =
       (int)std::min<int64_t>(std::min(kMaxChainHelpers, c->ncu - 1), (d.nft + hwaves - 1) / hwaves);
   // diagnostics (built with LSQ_TRSV_STAMPS=1): LSQ_CHAIN_TRACE=<file>
@@ -1223,7 +1224,7 @@ static void launch_trsv_chain(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
   static const char *trace_path = LSQ_TRSV_STAMPS ? getenv("LSQ_CHAIN_TRACE") : nullptr;
   unsigned long long *trace = nullptr;
   if (trace_path && hipMalloc(&trace, 4 * d.npass * sizeof(unsigned long long) + 64) != hipSuccess) trace = nullptr;
-  kern<<<1 + helpers, kChainThreads, lds, c->stream>>>(
+  kern<<<1 + helpers, chain_threads(E, EC), lds, c->stream>>>(
       (int)c->n, d.ta, d.tb, (int)d.nbatch, d.mci, (const T *)d.mval, (const T *)c->tdg, rhs, (int)d.nft, d.ft,
       d.fci, (const T *)d.fval, (int)d.npass, d.crow, d.cj, (const T *)d.cv, x, (T *)c->farbuf, c->flags + 3, trace);
   if (trace) {

@@ -8,18 +8,22 @@
 // level sets (a row's level is one more than the largest level of the rows it
 // reads). The entries of a row at level l are split by the level of the row
 // they read:
-//   late  - level l-1: the dependency chain itself;
-//   near  - levels l-D .. l-2 (D: near_levels option, 48 by default);
-//   far   - levels <= l-D-1: most of the entries.
-// One workgroup (the "main" block, x in LDS) walks the rows level by level
-// and computes x_i = (r_i - far_i - near_i - late_i) / M_ii. The far sums are
-// computed ahead of time by helper workgroups on other CUs, which can start on
-// a row as soon as the rows it reads at level <= l-D-1 are known, i.e. about D
-// levels before the main block reaches it. The main block moves every x_i to
-// global memory; helpers and the main block exchange x_i and far sums through
-// slots that hold a NaN sentinel until written, so no fence or counter is
-// shared between CUs. Within the main block an LDS counter of finished rows
-// orders the levels.
+//   late  - the K levels just below (K = 1, or the chain depth in chain mode):
+//           the dependency chain itself;
+//   near  - up to D levels below (D: near_levels option, 48 by default);
+//   far   - older: most of the entries.
+// Main workgroups walk the rows level by level and compute
+// x_i = r_i / M_ii - far_i - near_i - late_i (entries pre-divided by M_ii):
+// one workgroup with x in LDS, or several sharing the batches with x in
+// global memory, or, in chain mode, one workgroup whose wave 0 (the chain)
+// adds the late entries of every row while its other waves prepare the rest.
+// The far sums are computed ahead of time by helper workgroups on other CUs,
+// which can start on a row as soon as the rows it reads at level <= l-D-1 are
+// written, i.e. about D levels before the main part reaches it. Every x_i is
+// also written to global memory; all parties exchange x_i, far sums and (in
+// chain mode) row bases through slots that hold a NaN sentinel until written
+// and are polled until they do not, so no fence, counter or barrier is shared
+// between waves or CUs.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -116,10 +120,7 @@ __device__ __forceinline__ void st_sync(T *p, T v) {
 // Main-block task slots (level order; a batch of kMainR slots holds rows of one
 // level, padded with row -1):
 //   a = (row, k0, k1, nl): near entries [k0, k1), late entries [k1, k1 + nl)
-//   b = (pos, 0, f0, nf): the row's position in level order, far slots
-//       [f0, f0 + nf)
-// Chain steps (level order): (pos, rows): rows at positions [pos, pos + rows),
-// all of one level.
+//   b = (level, 0, f0, nf): the row's level, far slots [f0, f0 + nf)
 // Helper tasks (level order of their rows): (k0, k1, slot, probe): far
 // entries [k0, k1) summed into far slot `slot`; `probe` is a column of the
 // chunk at the highest level, polled before the chunk is gathered.
@@ -955,7 +956,8 @@ int build_levels(lsq_ctx *ctx) {
     // 1M x 10k sparse: 410 us at 3 levels and 2 entries per lane, 443 us at 6
     // and 4)
     const bool narrow = n <= 24 * (int64_t)std::min(Lf, Lb);
-    if (kc > 0 && narrow && 2 * n * (int64_t)es <= 160 * 1024) K = kc;
+    // an explicit depth takes chain mode also for wide levels
+    if (kc > 0 && (narrow || ctx->opt.chain_levels > 0) && 2 * n * (int64_t)es <= 160 * 1024) K = kc;
   }
   // entry counts per row and class
   int4 *dcnt;

@@ -341,10 +341,12 @@ def test_sparse_operator_kernels_agree(algo):
     assert rel(x.cpu().numpy(), xo) <= max(10 * rel(xo, xt), 1e-9)
 
 
-@pytest.mark.parametrize("name,chain", [("sparse", -1), ("sparse", 3), ("sparse", 12), ("udv", -1), ("udv", 0)])
+@pytest.mark.parametrize("name,chain", [("sparse", -1), ("sparse", 3), ("sparse", 12), ("udv", -1), ("udv", 0),
+                                        ("graph", 2), ("graph", 5)])
 def test_triangular_solve_modes(name, chain):
     """P r with the chain wave off and with several chain depths (sparse M with
-    narrow levels; dense M, one row per level) against the oracle."""
+    narrow levels; dense M, one row per level; the graph's wide levels, about
+    110 rows and several chain passes per level) against the oracle."""
     import torch
     print("\n[trsv mode] %s chain_levels=%d" % (name, chain), flush=True)
     p = FAMILIES[name]()

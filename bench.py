@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--mode", default="both", choices=["fp64", "fp32_refine", "both"],
                     help="both: FP64 (the reported value) and FP32 inner PCG + FP64 refinement, timed alike")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed-sweep", type=int, default=0,
+                    help="also run sampling seeds 1..N (float64) and report the mean and spread")
     ap.add_argument("--no-cg-baseline", action="store_true",
                     help="skip the unpreconditioned CG run (sweeps = 0) reported beside the main one")
     ap.add_argument("--atap-algo", type=int, default=0)
@@ -100,15 +102,15 @@ def main():
                    col_idx=torch.from_numpy(p.col_idx).cuda())
     torch.cuda.synchronize()
 
-    def step(mode, profile, sweeps=None):
+    def step(mode, profile, sweeps=None, seed=0):
         sweeps = cfg["sweeps"] if sweeps is None else sweeps
         if p.fmt == "dense":
-            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=sweeps, seed=0, mode=mode, profile=profile,
+            s = Solver(dev["A"], b, C_=cfg["C"], sweeps=sweeps, seed=seed, mode=mode, profile=profile,
                        atap_algo=args.atap_algo, near_levels=args.near_levels,
                        chain_levels=args.chain_levels, max_iter=args.max_iter)
         else:
             s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
-                       b=b, C_=cfg["C"], sweeps=sweeps, seed=0, mode=mode, profile=profile,
+                       b=b, C_=cfg["C"], sweeps=sweeps, seed=seed, mode=mode, profile=profile,
                        atap_algo=args.atap_algo, near_levels=args.near_levels,
                        chain_levels=args.chain_levels, max_iter=args.max_iter)
         x, info = s.solve()
@@ -218,6 +220,21 @@ def main():
             tf = rg["bytes"] / (rg["ms"] * 1e-3) / 1e12
             out[m]["gram"] = {"avg_ms": rg["ms"] / rg["launches"], "tflops": tf,
                               "peak_tflops": MFMA_PEAK_TFLOPS[m], "frac": tf / MFMA_PEAK_TFLOPS[m]}
+
+    if args.seed_sweep > 0:
+        # sampling seeds 1..N, one timed setup + solve each (float64): spread of
+        # the time and iteration count over the random sample
+        ts, its = [], []
+        for sd in range(1, args.seed_sweep + 1):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info, _ = step("fp64", False, seed=sd)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t1) * 1e3)
+            its.append(int(info["iters"]))
+        out["seed_sweep"] = {"seeds": args.seed_sweep, "ms_mean": float(np.mean(ts)), "ms_std": float(np.std(ts)),
+                             "iters_mean": float(np.mean(its)), "iters_std": float(np.std(its)),
+                             "iters_min": int(min(its)), "iters_max": int(max(its))}
 
     if not args.no_cg_baseline:
         # the paper's comparison column: CG on the normalised normal equations

@@ -27,7 +27,7 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}  # dense matrix-core pea
 # WRITE_SIZE runs (calibrated on a 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0), per workload and kernel; the profile summary in profiles/ gives the
 # commands. Only figures taken on the kernel code of this revision are listed.
-MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 61.05e6}
+MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 60.33e6}
 # triangular-solve kernel by lsq_info.trsv_mode
 TRSV_KERNEL = {0: "k_trsv (x in LDS)", 1: "k_trsv_chain", 2: "k_trsv (x in global memory)"}
 

@@ -46,18 +46,12 @@ struct Bits<float> {
   static constexpr U kSent = 0x7FA0BEEFu;
 };
 
-#ifndef LSQ_TRSV_THREADS
-#define LSQ_TRSV_THREADS 1024
-#endif
-constexpr int kTrsvThreads = LSQ_TRSV_THREADS, kTrsvWaves = kTrsvThreads / kWave;
-#ifndef LSQ_MAIN_G
-#define LSQ_MAIN_G 16
-#endif
-constexpr int kMainG = LSQ_MAIN_G, kMainR = kWave / kMainG;  // main block: lanes per row
+constexpr int kTrsvThreads = 1024, kTrsvWaves = kTrsvThreads / kWave;
+constexpr int kMainG = 16, kMainR = kWave / kMainG;  // main block: lanes per row, rows per batch
 constexpr int kFarE = 8, kFarChunk = kWave * kFarE;               // helpers: one wave per chunk
 // Entries reading the previous level are summed on the dependency chain by
 // up to kLateLanes lanes per row.
-constexpr int kLateLevels = 1, kLateLanes = 4;
+constexpr int kLateLanes = 4;
 constexpr int kMaxHelpers = 32;
 // clock stamps of the triangular solves, a diagnostic build only (reading
 // the clock slows the solve even when no stamp is written)
@@ -75,25 +69,9 @@ constexpr int chain_threads(int e, int ec) { return ec <= 4 && e <= 4 ? 1024 : 5
 constexpr int kMaxChainHelpers = 64;
 constexpr int kSpinLimit = 1 << 22;
 
-// wave priorities of the main block: default, while polling, on the chain
-#ifndef LSQ_PRIO_BASE
-#define LSQ_PRIO_BASE 2
-#endif
-#ifndef LSQ_PRIO_POLL
-#define LSQ_PRIO_POLL 0
-#endif
-#ifndef LSQ_PRIO_LATE
-#define LSQ_PRIO_LATE 2
-#endif
-#ifndef LSQ_POLL_SLEEP
-#define LSQ_POLL_SLEEP 0
-#endif
-#ifndef LSQ_POLL_UNROLL
-#define LSQ_POLL_UNROLL 1
-#endif
-#ifndef LSQ_WAKEUP
-#define LSQ_WAKEUP 0
-#endif
+// wave priorities of the main block's row waves: default and while polling
+// (the chain wave of chain mode runs at 3)
+constexpr int kPrioBase = 2, kPrioPoll = 0;
 
 // Bounded waiting: a wait that exceeds kSpinLimit polls raises *err, and every
 // wait gives up once *err is raised anywhere, so a failure ends all blocks.
@@ -177,7 +155,7 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
   const int NW = nmain * WW;
   const int g = lane / G, gl = lane % G;
   const int li = G - 1 - gl;  // late lanes: li < Q (the writer, lane G-1, is li = 0)
-  __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
+  __builtin_amdgcn_s_setprio(kPrioBase);
 
   // masked-off lanes read slot 0 and their products are discarded by selects
   auto xpoll = [&](int j) -> U { return __hip_atomic_load((U *)xs + j, __ATOMIC_RELAXED, scope); };
@@ -233,30 +211,16 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
   auto late_x = [&](int j) -> T {  // x_j, polled until written
     U u = xpoll(j);
     if (u == Bits<T>::kSent) {
-      __builtin_amdgcn_s_setprio(LSQ_PRIO_POLL);
+      __builtin_amdgcn_s_setprio(kPrioPoll);
       int spins = 0;
-#if LSQ_POLL_UNROLL
       do {
-        if (LSQ_POLL_SLEEP) __builtin_amdgcn_s_sleep(LSQ_POLL_SLEEP);
         if (give_up(spins, err)) {
           u = 0;
           break;
         }
         u = xpoll(j);
       } while (u == Bits<T>::kSent);
-#else
-#pragma unroll 1
-      for (;;) {
-        if (LSQ_POLL_SLEEP) __builtin_amdgcn_s_sleep(LSQ_POLL_SLEEP);
-        u = xpoll(j);
-        if (u != Bits<T>::kSent) break;
-        if (give_up(spins, err)) {
-          u = 0;
-          break;
-        }
-      }
-#endif
-      __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
+      __builtin_amdgcn_s_setprio(kPrioBase);
     }
     return __builtin_bit_cast(T, u);
   };
@@ -306,7 +270,6 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
       const int4 a = ta[slot];
       for (int k = a.z + Q + li; li < Q && k < a.z + d.nl; k += Q) lacc += mval[k] * late_x(mci[k]);
     }
-    if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_LATE);
     const unsigned long long t_ready = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
     lacc = dpp_group_sum<Q>(lacc);
     if (d.row >= 0 && gl == G - 1) {
@@ -314,7 +277,6 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
       if (LDSX) __hip_atomic_store((U *)xs + d.row, __builtin_bit_cast(U, xi), __ATOMIC_RELAXED, scope);
       const unsigned long long t_pub = LSQ_TRSV_STAMPS && trace ? __builtin_readcyclecounter() : 0;
       st_sync(x + d.row, xi);
-      if (LSQ_WAKEUP) __asm__ volatile("s_wakeup");
       if (LSQ_TRSV_STAMPS && trace) {  // diagnostics (shader clock): start, late start, publish, level
         trace[8 * slot] = t_in;
         trace[8 * slot + 1] = t_go;
@@ -325,7 +287,6 @@ __device__ __forceinline__ void trsv_main(int n, int nmain, const int4 *__restri
         trace[8 * slot + 6] = t_read;
       }
     }
-    if (LSQ_PRIO_LATE != LSQ_PRIO_BASE) __builtin_amdgcn_s_setprio(LSQ_PRIO_BASE);
   };
   auto step = [&](int bt, const Buf &dcur, const MainTask &nx, Buf &dnx, MainTask &fetch) {
     fetch = main_task<R>(bt + 2 * NW, g, nbatch, ta, tb);

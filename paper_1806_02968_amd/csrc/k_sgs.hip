@@ -465,9 +465,11 @@ __device__ __forceinline__ void trsv_chain(int npass, const int32_t *__restrict_
     const bool on = c.row >= 0;
     U bu = lds_ld(bs, on ? c.row : 0);
     T pr[EC];
+    bool inpass = false;
 #pragma unroll
     for (int e = 0; e < EC; ++e) {
       const bool ok = c.j[e] >= 0;
+      inpass |= c.j[e] <= -2;
       const U xu = lds_ld(xs, ok ? c.j[e] : 0);
       pr[e] = ok ? c.v[e] * __builtin_bit_cast(T, xu) : (T)0;
     }
@@ -487,7 +489,27 @@ __device__ __forceinline__ void trsv_chain(int npass, const int32_t *__restrict_
     }
     const unsigned long long t1 = LSQ_TRSV_STAMPS ? __builtin_readcyclecounter() : 0;
     const T acc = dpp_group_sum<kChainLanes>(pr[0]);
-    const T xi = __builtin_bit_cast(T, bu) - acc;
+    T xi = __builtin_bit_cast(T, bu) - acc;
+    if (__ballot(inpass) != 0) {
+      // second-level rows of the pass: their entries reading first-level
+      // rows take those rows' x from the lanes that just formed them (the
+      // first-level rows have no such entries, so their x is final here)
+      const int lo = __double2loint((double)xi), hi = __double2hiint((double)xi);
+      T pin[EC];
+#pragma unroll
+      for (int e = 0; e < EC; ++e) {
+        const int src = c.j[e] <= -2 ? -2 - c.j[e] : lane;
+        const int xl = __builtin_amdgcn_ds_bpermute(src * 4, lo);
+        const int xh = __builtin_amdgcn_ds_bpermute(src * 4, hi);
+        const T xv = (T)__hiloint2double(xh, xl);
+        pin[e] = c.j[e] <= -2 ? c.v[e] * xv : (T)0;
+      }
+#pragma unroll
+      for (int w = 1; w < EC; w *= 2)
+#pragma unroll
+        for (int e = 0; e + w < EC; e += 2 * w) pin[e] += pin[e + w];
+      xi -= dpp_group_sum<kChainLanes>(pin[0]);
+    }
     if (on && lane % kChainLanes == 0) {
       __hip_atomic_store((U *)xs + c.row, __builtin_bit_cast(U, xi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       st_sync(x + c.row, xi);
@@ -808,7 +830,9 @@ __global__ __launch_bounds__(256) void k_far_probe(int nft, int4 *__restrict__ f
   if (lane == 0) ft[c].w = (int)(key & 0x7FFFFFFF);
 }
 
-// chain passes from (row, first chain entry, chain entries) per row group
+// chain passes from (row, first chain entry, chain entries, second level of
+// its pass) per row group; an entry of a second-level row that reads a row
+// of the same pass is stored as column -2 - (first lane of that row's group)
 template <typename T>
 __global__ __launch_bounds__(256) void k_chain_pack(int npass, int ec, const int4 *__restrict__ cq,
                                                     const int32_t *__restrict__ mci, const T *__restrict__ mval,
@@ -823,7 +847,13 @@ __global__ __launch_bounds__(256) void k_chain_pack(int npass, int ec, const int
   for (int e = 0; e < ec; ++e) {
     const int k = lane % kChainLanes + kChainLanes * e;
     const bool ok = q.x >= 0 && k < q.z;
-    cj[(p * ec + e) * kWave + lane] = ok ? mci[q.y + k] : -1;
+    int j = ok ? mci[q.y + k] : -1;
+    if (ok && q.w == 1)
+      for (int a = 0; a < kChainRows; ++a) {
+        const int4 qa = cq[p * kChainRows + a];
+        if (qa.w == 0 && qa.x == j) j = -2 - a * kChainLanes;
+      }
+    cj[(p * ec + e) * kWave + lane] = j;
     cv[(p * ec + e) * kWave + lane] = ok ? mval[q.y + k] : (T)0;
   }
 }
@@ -979,7 +1009,7 @@ int build_levels(lsq_ctx *ctx) {
         byl[fill[lev[i]]++] = (int32_t)i;
       }
     }
-    std::vector<int4> ta, tb, ft, cq;
+    std::vector<int4> ta, tb, ft, cq, crows(chain ? n : 0);
     ta.reserve(n + (size_t)L * R);
     tb.reserve(n + (size_t)L * R);
     int64_t mpos = 0, fpos = 0, slot = 0;
@@ -990,7 +1020,7 @@ int build_levels(lsq_ctx *ctx) {
         const int32_t nf = (c.z + kFarChunk - 1) / kFarChunk;
         info[i] = make_int4((int32_t)mpos, (int32_t)fpos, 0, 0);
         ta.push_back(make_int4(i, (int32_t)mpos, (int32_t)(mpos + c.x), c.y));
-        if (chain) cq.push_back(make_int4(i, (int32_t)(mpos + c.x), c.y, 0));
+        if (chain) crows[q] = make_int4(i, (int32_t)(mpos + c.x), c.y, 0);
         tb.push_back(make_int4(l, 0, (int32_t)slot, nf));
         maxnear = std::max(maxnear, c.x);
         for (int32_t f = 0; f < nf; ++f) {
@@ -1006,7 +1036,20 @@ int build_levels(lsq_ctx *ctx) {
         ta.push_back(make_int4(-1, 0, 0, 0));
         tb.push_back(make_int4(0, 0, 0, 0));
       }
-      while (chain && cq.size() % kChainRows) cq.push_back(make_int4(-1, 0, 0, 0));
+    }
+    // chain passes: two consecutive levels share a pass when their rows fit
+    // (the second level's rows, marked w = 1, take their entries reading the
+    // first level from the lanes that computed them); other levels fill
+    // passes of up to kChainRows rows
+    for (int32_t l = 0; chain && l < L;) {
+      const int64_t na = lc[l + 1] - lc[l];
+      const int64_t nb2 = l + 1 < L ? lc[l + 2] - lc[l + 1] : (int64_t)kChainRows + 1;
+      const bool pair = na + nb2 <= kChainRows;
+      for (int64_t q = lc[l]; q < lc[l + 1]; ++q) cq.push_back(crows[q]);
+      if (pair)
+        for (int64_t q = lc[l + 1]; q < lc[l + 2]; ++q) cq.push_back(make_int4(crows[q].x, crows[q].y, crows[q].z, 1));
+      while (cq.size() % kChainRows) cq.push_back(make_int4(-1, 0, 0, 0));
+      l += pair ? 2 : 1;
     }
     if (mpos >= INT32_MAX || fpos >= INT32_MAX || slot >= INT32_MAX) {
       too_big = true;

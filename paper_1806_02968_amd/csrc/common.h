@@ -206,6 +206,7 @@ void launch_fill_f32(float *x, int64_t n, float v, hipStream_t st);
 void launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t st);
 void launch_colnorm_dense(const lsq_ctx *c, double *part, int nblk, hipStream_t st);
 void launch_colnorm_csr(const lsq_ctx *c, double *sumsq, hipStream_t st);
+int launch_colnorm_csr_part(const lsq_ctx *c, double *part, hipStream_t st);
 void launch_colnorm_finish(int64_t n, const double *part, int nblk, double *D, double *invD,
                            float *invD32, int32_t *flags, hipStream_t st);
 void launch_rowweight(const lsq_ctx *c, double *w, int32_t *flags, hipStream_t st);

@@ -231,7 +231,10 @@ __global__ void k_csc_fill(int64_t sd, const int64_t *__restrict__ urow, const i
   }
 }
 
-template <typename TA>
+// G lanes per CSC entry (column j of sampled row r): lane t forms the
+// products with the row's entries t, t + G, ..., so a group reads the row and
+// writes its products contiguously
+template <typename TA, int G>
 __global__ void k_expand(int64_t E, const int32_t *__restrict__ csc_r, const int64_t *__restrict__ csc_k,
                          const int64_t *__restrict__ poff, const int64_t *__restrict__ urow,
                          const int32_t *__restrict__ ucnt, const int64_t *__restrict__ rp,
@@ -239,19 +242,23 @@ __global__ void k_expand(int64_t E, const int32_t *__restrict__ csc_r, const int
                          const double *__restrict__ invD, const double *__restrict__ Wp, double s,
                          uint64_t *__restrict__ key, double *__restrict__ val) {
   const double W = *Wp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+  const int t = threadIdx.x % G;
+  const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t ng = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t e = g0; e < E; e += ng) {
     const int32_t r = csc_r[e];
     const int64_t k = csc_k[e];
     const int64_t i = urow[r];
     const int32_t j = ci[k];
     const double coef = (double)ucnt[r] * W / (s * w[i]);
     const double aj = (double)v[k] * invD[j];
-    int64_t o = poff[e];
-    for (int64_t q = rp[i]; q < rp[i + 1]; ++q, ++o) {
+    const int64_t q0 = rp[i], q1 = rp[i + 1];
+    const int64_t o = poff[e] - q0;
+    for (int64_t q = q0 + t; q < q1; q += G) {
       const int32_t l = ci[q];
       const double al = (double)v[q] * invD[l];
-      key[o] = ((uint64_t)(uint32_t)l << 32) | (uint32_t)r;
-      val[o] = coef * (aj * al);
+      key[o + q] = ((uint64_t)(uint32_t)l << 32) | (uint32_t)r;
+      val[o + q] = coef * (aj * al);
     }
   }
 }
@@ -538,17 +545,34 @@ int build_sparse_gram(lsq_ctx *ctx) {
   int64_t *ucount = (int64_t *)lsq_alloc(ctx, (n + 1) * sizeof(int64_t));
   if (!key || !val || !ocol || !oval || !ucount) return LSQ_ENOMEM;
   {
-    int64_t b = (E + 255) / 256;
+    // lanes per CSC entry from the average row length of A
+    const double avg = (double)ctx->nnz / (double)std::max<int64_t>(1, ctx->m);
+    const int G = avg <= 2 ? 2 : avg <= 4 ? 4 : avg <= 8 ? 8 : avg <= 16 ? 16 : 32;
+    int64_t b = (E * G + 255) / 256;
     if (b > 16384) b = 16384;
     if (b < 1) b = 1;
-    if (ctx->dtype == LSQ_F64)
-      k_expand<double><<<(unsigned)b, 256, 0, st>>>(E, csc_r, csc_k, poff, ctx->urow, ctx->ucnt, ctx->rp, ctx->ci,
-                                                    (const double *)ctx->A, ctx->w, ctx->invD, ctx->cdf + ctx->m - 1,
-                                                    (double)ctx->s, key, val);
-    else
-      k_expand<float><<<(unsigned)b, 256, 0, st>>>(E, csc_r, csc_k, poff, ctx->urow, ctx->ucnt, ctx->rp, ctx->ci,
-                                                   (const float *)ctx->A, ctx->w, ctx->invD, ctx->cdf + ctx->m - 1,
-                                                   (double)ctx->s, key, val);
+    const double *Wp = ctx->cdf + ctx->m - 1;
+#define LSQ_EXPAND(TA, GG)                                                                                        \
+  k_expand<TA, GG><<<(unsigned)b, 256, 0, st>>>(E, csc_r, csc_k, poff, ctx->urow, ctx->ucnt, ctx->rp, ctx->ci, \
+                                                (const TA *)ctx->A, ctx->w, ctx->invD, Wp, (double)ctx->s, key, val)
+    if (ctx->dtype == LSQ_F64) {
+      switch (G) {
+        case 2: LSQ_EXPAND(double, 2); break;
+        case 4: LSQ_EXPAND(double, 4); break;
+        case 8: LSQ_EXPAND(double, 8); break;
+        case 16: LSQ_EXPAND(double, 16); break;
+        default: LSQ_EXPAND(double, 32); break;
+      }
+    } else {
+      switch (G) {
+        case 2: LSQ_EXPAND(float, 2); break;
+        case 4: LSQ_EXPAND(float, 4); break;
+        case 8: LSQ_EXPAND(float, 8); break;
+        case 16: LSQ_EXPAND(float, 16); break;
+        default: LSQ_EXPAND(float, 32); break;
+      }
+    }
+#undef LSQ_EXPAND
   }
   // the product offset of column j's first CSC entry: poff[cptr[j]]
   {

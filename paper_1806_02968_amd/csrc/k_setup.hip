@@ -2,6 +2,8 @@
 // normalised matrix (Eq. R2P), the inclusive CDF of the weights, the i.i.d.
 // draws of Algorithm 1 from a Philox4x64-10 counter generator, and the
 // compaction of the drawn rows into (row, multiplicity) pairs.
+#include <algorithm>
+
 #include "common.h"
 
 namespace lsq {
@@ -90,6 +92,51 @@ void launch_colnorm_dense(const lsq_ctx *c, double *part, int nblk, hipStream_t 
     k_colnorm_dense<double><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, (const double *)c->A, part, rpb);
   else
     k_colnorm_dense<float><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, (const float *)c->A, part, rpb);
+}
+
+// column sums of squares of a CSR A into per-workgroup partial rows: block b
+// adds the entries of its nnz range into an LDS row of n sums (no contention
+// on global memory) and writes it to part row b
+template <typename TA>
+__global__ __launch_bounds__(1024) void k_colnorm_csr_lds(int64_t nnz, int n, const int32_t *__restrict__ ci,
+                                                          const TA *__restrict__ v, double *__restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *acc = (double *)smem;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) acc[j] = 0.0;
+  __syncthreads();
+  const int64_t per = (nnz + gridDim.x - 1) / gridDim.x;
+  const int64_t k0 = blockIdx.x * per, k1 = k0 + per < nnz ? k0 + per : nnz;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const double a = (double)v[k];
+    atomicAdd(&acc[ci[k]], a * a);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) part[blockIdx.x * (int64_t)n + j] = acc[j];
+}
+
+// returns the number of partial rows written to part
+int launch_colnorm_csr_part(const lsq_ctx *c, double *part, hipStream_t st) {
+  const int64_t n = c->n;
+  if (n * 8 > 128 * 1024 || c->part_bytes < (size_t)256 * n * sizeof(double)) {
+    launch_colnorm_csr(c, part, st);
+    return 1;
+  }
+  const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(256, c->nnz / 4096));
+  const size_t lds = n * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_colnorm_csr_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              128 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_colnorm_csr_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              128 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  if (c->dtype == LSQ_F64)
+    k_colnorm_csr_lds<double><<<nblk, 1024, lds, st>>>(c->nnz, (int)n, c->ci, (const double *)c->A, part);
+  else
+    k_colnorm_csr_lds<float><<<nblk, 1024, lds, st>>>(c->nnz, (int)n, c->ci, (const float *)c->A, part);
+  return nblk;
 }
 
 void launch_colnorm_csr(const lsq_ctx *c, double *sumsq, hipStream_t st) {

@@ -356,8 +356,8 @@ static int setup_impl(lsq_ctx *ctx) {
     launch_colnorm_dense(ctx, ctx->part, nblk, st);
     launch_colnorm_finish(n, ctx->part, nblk, ctx->D, ctx->invD, ctx->invD32, ctx->flags, st);
   } else {
-    launch_colnorm_csr(ctx, ctx->part, st);
-    launch_colnorm_finish(n, ctx->part, 1, ctx->D, ctx->invD, ctx->invD32, ctx->flags, st);
+    const int nblk = launch_colnorm_csr_part(ctx, ctx->part, st);
+    launch_colnorm_finish(n, ctx->part, nblk, ctx->D, ctx->invD, ctx->invD32, ctx->flags, st);
   }
   LSQ_HIP_CHECK(hipMemcpyAsync(hflags, ctx->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   LSQ_HIP_CHECK(hipStreamSynchronize(st));

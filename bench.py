@@ -27,7 +27,7 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}  # dense matrix-core pea
 # WRITE_SIZE runs (calibrated on a 1 GiB copy: FETCH_SIZE x 2.0, WRITE_SIZE
 # x 1.0), per workload and kernel; the profile summary in profiles/ gives the
 # commands. Only figures taken on the kernel code of this revision are listed.
-MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 60.33e6}
+MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 58.88e6}
 # triangular-solve kernel by lsq_info.trsv_mode
 TRSV_KERNEL = {0: "k_trsv (x in LDS)", 1: "k_trsv_chain", 2: "k_trsv (x in global memory)"}
 
@@ -197,6 +197,7 @@ def main():
         "atap_frac": (atap_gbs / HBM_PEAK_GBS) if atap_gbs else None,
         "atap_algo": int(last["atap_algo"]),
         "trsv_kernel": TRSV_KERNEL[int(last["trsv_mode"])],
+        "chain_levels": int(last["chain_levels"]), "chain_max": int(last["chain_max"]),
         "kernels": kernels,
         "roofline": roofline,
     }
@@ -224,7 +225,7 @@ def main():
     if args.seed_sweep > 0:
         # sampling seeds 1..N, one timed setup + solve each (float64): spread of
         # the time and iteration count over the random sample
-        ts, its = [], []
+        ts, its, chains = [], [], []
         for sd in range(1, args.seed_sweep + 1):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -232,9 +233,12 @@ def main():
             torch.cuda.synchronize()
             ts.append((time.perf_counter() - t1) * 1e3)
             its.append(int(info["iters"]))
+            chains.append([int(info["chain_levels"]), int(info["chain_max"])])
         out["seed_sweep"] = {"seeds": args.seed_sweep, "ms_mean": float(np.mean(ts)), "ms_std": float(np.std(ts)),
+                             "ms_min": float(min(ts)), "ms_max": float(max(ts)),
                              "iters_mean": float(np.mean(its)), "iters_std": float(np.std(its)),
-                             "iters_min": int(min(its)), "iters_max": int(max(its))}
+                             "iters_min": int(min(its)), "iters_max": int(max(its)),
+                             "chain_levels_and_max": chains}
 
     if not args.no_cg_baseline:
         # the paper's comparison column: CG on the normalised normal equations

@@ -102,8 +102,9 @@ typedef struct {
                           set explicitly), one wave sums
                           the entries reading rows at most this many levels
                           below (0: automatic, the most levels from 6 down to
-                          2 that keep at most 8 such entries per row; -1: off;
-                          at most 64)                                        */
+                          3 that keep at most 8 such entries per row, else 3
+                          when it keeps at most 32, else 2 when that does;
+                          -1: off; at most 64)                               */
 } lsq_options;
 
 /* Fills *opt with the defaults above. */
@@ -134,6 +135,12 @@ typedef struct {
   int32_t atap_algo;    /* sparse A: the A^T(Ap) kernel in use (values of
                            lsq_options.atap_algo); dense A: the option as
                            given (0: chosen per call by the vector length)    */
+  int32_t chain_levels; /* chain mode: the levels below a row whose entries
+                           are summed on the chain (0 outside chain mode)     */
+  int32_t chain_max;    /* chain mode: the most such entries in one row (the
+                           chain wave holds 4 rows of 16 lanes' worth: the
+                           smallest power of two >= 2 and >= chain_max / 4
+                           entries per lane); 0 outside chain mode            */
 } lsq_info;
 
 typedef struct lsq_ctx lsq_ctx;

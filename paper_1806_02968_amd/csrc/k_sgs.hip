@@ -655,9 +655,13 @@ __device__ __forceinline__ void tri_range(bool upper, int i, const int32_t *__re
 // more than the largest level among the rows it reads, waited for in LDS (or
 // global memory when n ints do not fit) where levels start as -1. Rows read
 // only rows earlier in the solve order, so the earliest unfinished row can
-// always finish (all blocks are resident). A wave requests the next row's
-// column indices before it waits for the current row's levels; all reads are
-// issued from clamped indices before any is waited for.
+// always finish (all blocks are resident).
+//
+// Loads are kept off the dependency chain: the row bounds of a wave's next 64
+// rows sit one per lane, loaded a chunk ahead and taken with readlane, and
+// the column indices of a row are requested two rows before its levels are
+// read, in three row buffers with fixed roles (no register copies of values
+// still in flight). All reads use clamped indices.
 template <bool LDSL>
 __global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, int nb, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
@@ -673,67 +677,104 @@ __global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, int nb, const in
     for (int i = threadIdx.x; i < n; i += kTrsvThreads) lv[i] = -1;
   __syncthreads();  // the global array starts at -1 (set before the launch)
   const int lane = threadIdx.x % kWave;
-  const int gw = (int)(blockIdx.x % nb) * kTrsvWaves + threadIdx.x / kWave, W = nb * kTrsvWaves;
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x % nb) * kTrsvWaves + (int)threadIdx.x / kWave);
+  const int W = nb * kTrsvWaves;
   auto ld_level = [&](int j) -> int { return __hip_atomic_load(lv + j, __ATOMIC_RELAXED, scope); };
+  // the wave's k-th row is q = gw + k W of the solve order; rows past n are empty
+  auto valid = [&](int k) { return (int64_t)gw + (int64_t)k * W < n; };
+  // bounds of the wave's rows 64 c .. 64 c + 63, lane t holding row 64 c + t
+  // (raw loads: the strict upper part starts one past the diagonal, added
+  // when the bound is taken, so no arithmetic waits for them here)
+  const int32_t *pa = upper ? dg : rp;
+  const int32_t *pb = upper ? rp + 1 : dg;
+  auto chunk = [&](int c, int &ri, int &ra, int &rb) {
+    const int64_t q = (int64_t)gw + (int64_t)(64 * c + lane) * W;
+    const int qq = q < n ? (int)q : n - 1;
+    ri = upper ? n - 1 - qq : qq;
+    ra = pa[ri];
+    rb = pb[ri];
+  };
+  int ci0, ca0, cb0, ci1, ca1, cb1;  // current and next chunk
+  chunk(0, ci0, ca0, cb0);
+  chunk(1, ci1, ca1, cb1);
+  int chunk_next = 2;
   struct Row {
     int i, a, b;
     int j[E];
   };
-  // row bounds and the first E column indices per lane (clamped reads)
-  auto fetch = [&](int q, Row &r) {
-    const int qq = q < n ? q : n - 1;
-    r.i = upper ? n - 1 - qq : qq;
-    tri_range(upper, r.i, rp, dg, &r.a, &r.b);
-    if (q >= n) r.b = r.a;
+  // bounds from the chunk and the first E column indices per lane
+  auto fetch = [&](int k, Row &r) {
+    const int t = k & 63;
+    r.i = __builtin_amdgcn_readlane(ci0, t);
+    r.a = __builtin_amdgcn_readlane(ca0, t) + (upper ? 1 : 0);
+    const int b = __builtin_amdgcn_readlane(cb0, t);
+    r.b = valid(k) ? b : r.a;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int k = r.a + lane + kWave * e;
-      r.j[e] = ci[k < r.b ? k : (r.b > r.a ? r.a : 0)];
+      const int kk = r.a + lane + kWave * e;
+      r.j[e] = ci[kk < r.b ? kk : (r.b > r.a ? r.a : 0)];
+    }
+    if (t == 63) {
+      ci0 = ci1, ca0 = ca1, cb0 = cb1;
+      chunk(chunk_next++, ci1, ca1, cb1);
     }
   };
-  auto level = [&](Row &r) -> int {
-    int mx = -1, spins = 0;
-    for (int k0 = r.a; k0 < r.b; k0 += kWave * E) {
-      if (k0 != r.a) {  // rows longer than E per lane (rare): the next chunk
+  // largest level among the entries k0 + lane + 64 e < b (column indices j)
+  auto chunk_level = [&](const int (&j)[E], int k0, int b, int mx) -> int {
+    int v[E], pend = 0, spins = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int k = k0 + lane + kWave * e;
-          r.j[e] = ci[k < r.b ? k : k0];
-        }
-      }
-      int v[E], pend = 0;
+    for (int e = 0; e < E; ++e) v[e] = ld_level(j[e]);
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = ld_level(r.j[e]);
+    for (int e = 0; e < E; ++e) {
+      const bool on = k0 + lane + kWave * e < b;
+      pend |= on && v[e] < 0 ? 1 << e : 0;
+      mx = on && v[e] > mx ? v[e] : mx;
+    }
+    while (pend) {  // levels not yet known: wait for them
+      __builtin_amdgcn_s_sleep(1);
+      if (give_up(spins, err)) break;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const bool on = k0 + lane + kWave * e < r.b;
-        pend |= on && v[e] < 0 ? 1 << e : 0;
-        mx = on && v[e] > mx ? v[e] : mx;
-      }
-      while (pend) {  // levels not yet known: wait for them
-        __builtin_amdgcn_s_sleep(1);
-        if (give_up(spins, err)) break;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if (!((pend >> e) & 1)) continue;
-          const int u = ld_level(r.j[e]);
-          if (u >= 0) {
-            mx = u > mx ? u : mx;
-            pend &= ~(1 << e);
-          }
+        if (!((pend >> e) & 1)) continue;
+        const int u = ld_level(j[e]);
+        if (u >= 0) {
+          mx = u > mx ? u : mx;
+          pend &= ~(1 << e);
         }
       }
     }
     return mx;
   };
-  Row cur, nxt;
-  fetch(gw, cur);
-  for (int q = gw; q < n; q += W) {
-    fetch(q + W, nxt);
-    int mx = level(cur);
+  auto level = [&](const Row &r) -> int {
+    int mx = chunk_level(r.j, r.a, r.b, -1);
+    // rows longer than E entries per lane (rare): further chunks, in registers
+    // of their own so that the prefetched rows' loads are not waited for
+    for (int k0 = r.a + kWave * E; k0 < r.b; k0 += kWave * E) {
+      int j[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = k0 + lane + kWave * e;
+        j[e] = ci[k < r.b ? k : k0];
+      }
+      mx = chunk_level(j, k0, r.b, mx);
+    }
+    return mx;
+  };
+  auto proc = [&](int k, Row &r) {
+    int mx = level(r);
     mx = dpp_wave_max(mx);
-    if (lane == kWave - 1) __hip_atomic_store(lv + cur.i, mx + 1, __ATOMIC_RELAXED, scope);
-    cur = nxt;
+    if (lane == kWave - 1 && valid(k)) __hip_atomic_store(lv + r.i, mx + 1, __ATOMIC_RELAXED, scope);
+  };
+  Row r0, r1, r2;
+  fetch(0, r0);
+  fetch(1, r1);
+  for (int k = 0; valid(k); k += 3) {
+    fetch(k + 2, r2);
+    proc(k, r0);
+    fetch(k + 3, r0);
+    proc(k + 1, r1);
+    fetch(k + 4, r1);
+    proc(k + 2, r2);
   }
   if (LDSL) {
     __syncthreads();
@@ -958,10 +999,12 @@ int build_levels(lsq_ctx *ctx) {
       Lb = std::max(Lb, lev_b[i] + 1);
     }
     const int kc = ctx->opt.chain_levels > 0 ? ctx->opt.chain_levels : (ctx->opt.chain_levels < 0 ? 0 : 6);
-    // (0: automatic, from 6 down to 2 until the chain holds at most 2 entries
+    // (0: automatic, from 6 down to 3 until the chain holds at most 2 entries
     // per lane: each chain entry is a memory load per pass for the chain wave;
     // 1M x 10k sparse: 410 us at 3 levels and 2 entries per lane, 443 us at 6
-    // and 4)
+    // and 4. Not below 3 while 8 entries per lane suffice: two consecutive
+    // levels share a pass only from 3 levels on, and a solve in single-level
+    // passes takes about 1.5 x as long)
     const bool narrow = n <= 24 * (int64_t)std::min(Lf, Lb);
     // an explicit depth takes chain mode also for wide levels
     if (kc > 0 && (narrow || ctx->opt.chain_levels > 0) && 2 * n * (int64_t)es <= 160 * 1024) K = kc;
@@ -989,7 +1032,8 @@ int build_levels(lsq_ctx *ctx) {
     for (int64_t i = 0; i < 2 * n; ++i) maxlate = std::max(maxlate, hcnt[i].y);
     // the chain holds at most 8 entries per lane
     if (K == 1) break;
-    if (ctx->opt.chain_levels == 0 && maxlate > kChainLanes * 2 && K > 2) {
+    if (ctx->opt.chain_levels == 0 &&
+        ((maxlate > kChainLanes * 2 && K > 3) || (maxlate > kChainLanes * 8 && K > 2))) {
       --K;
       continue;
     }
@@ -1002,6 +1046,8 @@ int build_levels(lsq_ctx *ctx) {
   ctx->trsv_chain = chain;
   ctx->trsv_ec = ec;
   ctx->info.trsv_mode = chain ? 1 : (n * (int64_t)es <= 150 * 1024 ? 0 : 2);
+  ctx->info.chain_levels = chain ? K : 0;
+  ctx->info.chain_max = chain ? maxlate : 0;
   constexpr int R = kMainR;
   bool too_big = false;
   int32_t maxnear = 0;

@@ -24,7 +24,7 @@ int lsq_hip_fail(lsq_ctx *ctx, hipError_t e, const char *what) {
 }
 
 // Device memory: a process-wide cache of freed blocks, keyed by device and
-// rounded size. A context's blocks return to the cache when it is destroyed
+// rounded size (a request takes the smallest fitting block up to 25 % larger). A context's blocks return to the cache when it is destroyed
 // (after its stream has drained) or when a temporary is released (after a
 // stream synchronisation), so repeated setups reuse the same blocks instead of
 // paying hipMalloc/hipFree every time. Blocks stay allocated until the process
@@ -44,20 +44,27 @@ static size_t round_size(size_t bytes) {
 void *lsq_alloc(lsq_ctx *ctx, size_t bytes) {
   const size_t rb = round_size(bytes < 16 ? 16 : bytes);
   void *p = nullptr;
+  size_t got = rb;
   {
+    // the smallest cached block of at least rb and at most rb + rb/4 bytes:
+    // sizes that depend on the data (the sample, the Gram pattern) change
+    // from one setup to the next
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    auto it = g_blocks.find({ctx->device, rb});
-    if (it != g_blocks.end() && !it->second.empty()) {
-      p = it->second.back();
-      it->second.pop_back();
-    }
+    for (auto it = g_blocks.lower_bound({ctx->device, rb});
+         it != g_blocks.end() && it->first.first == ctx->device && it->first.second <= rb + rb / 4; ++it)
+      if (!it->second.empty()) {
+        p = it->second.back();
+        it->second.pop_back();
+        got = it->first.second;
+        break;
+      }
   }
   if (!p && hipMalloc(&p, rb) != hipSuccess) {
     (void)hipGetLastError();
     ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
     return nullptr;
   }
-  ctx->allocs.push_back(Dev{p, rb});
+  ctx->allocs.push_back(Dev{p, got});
   return p;
 }
 

@@ -61,7 +61,8 @@ class Info(C.Structure):
                 ("outer_iters", C.c_int64), ("replacements", C.c_int64), ("W", C.c_double),
                 ("relres", C.c_double), ("relres_true", C.c_double), ("setup_ms", C.c_double),
                 ("solve_ms", C.c_double), ("converged", C.c_int32), ("status", C.c_int32),
-                ("trsv_mode", C.c_int32), ("atap_algo", C.c_int32)]
+                ("trsv_mode", C.c_int32), ("atap_algo", C.c_int32),
+                ("chain_levels", C.c_int32), ("chain_max", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

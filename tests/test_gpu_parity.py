@@ -80,6 +80,47 @@ def test_gram_matrix(case):
     assert s.info()["diag_fixes"] == o.info()["diag_fixes"]
 
 
+def _level_counts(rp, ci, n):
+    """Level sets of the forward and backward solves over a CSR pattern, by
+    their definition (Algorithm 3's schedule): a row's level is one more than
+    the largest level among the rows its strict lower (forward) or strict
+    upper (backward) entries read, 0 when it reads none."""
+    fwd = np.zeros(n, dtype=np.int64)
+    bwd = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        c = ci[rp[i]:rp[i + 1]]
+        c = c[c < i]
+        fwd[i] = fwd[c].max() + 1 if c.size else 0
+    for i in range(n - 1, -1, -1):
+        c = ci[rp[i]:rp[i + 1]]
+        c = c[c > i]
+        bwd[i] = bwd[c].max() + 1 if c.size else 0
+    return int(fwd.max()) + 1, int(bwd.max()) + 1
+
+
+def test_level_sets(case):
+    s = case["solver"]
+    rp, ci, _ = s.M_csr()
+    lf, lb = _level_counts(rp, ci, s.n)
+    info = s.info()
+    assert (info["levels_fwd"], info["levels_bwd"]) == (lf, lb)
+
+
+@pytest.mark.parametrize("shape", [(200_000, 6000, 10), (100_000, 1_200_000, 0)])
+def test_level_sets_many_rows_per_wave(shape):
+    """Level analysis where each wave takes several chunks of 64 rows: a sparse
+    M whose levels are kept in LDS (n = 6000, one workgroup per triangle) and a
+    graph M with levels in global memory (n = 99,999, 64 workgroups per
+    triangle)."""
+    m, n_or_e, k = shape
+    p = sparse_rowscaled(m=m, n=n_or_e, k=k, seed=12) if k else er_incidence(m, n_or_e, seed=9)
+    print("\n[levels] m=%d n=%d" % (p.m, p.n), flush=True)
+    s, _ = make_solver(p, C_=4.0, sweeps=1, seed=0)
+    rp, ci, _ = s.M_csr()
+    info = s.info()
+    assert (info["levels_fwd"], info["levels_bwd"]) == _level_counts(rp, ci, s.n)
+
+
 def test_operator_products(case):
     import torch
     s = case["solver"]

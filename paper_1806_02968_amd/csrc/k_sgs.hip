@@ -25,6 +25,7 @@
 // and are polled until they do not, so no fence, counter or barrier is shared
 // between waves or CUs.
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -730,18 +731,30 @@ __global__ __launch_bounds__(kTrsvThreads) void k_levels(int n, int nb, const in
       pend |= on && v[e] < 0 ? 1 << e : 0;
       mx = on && v[e] > mx ? v[e] : mx;
     }
-    while (pend) {  // levels not yet known: wait for them
-      __builtin_amdgcn_s_sleep(1);
-      if (give_up(spins, err)) break;
+    bool gave_up = false;
+    while (pend && !gave_up) {  // levels not yet known: wait for them
+      // one pending entry at a time, the row latest in the solve order first
+      // (when it is done the others mostly are): one read per poll keeps
+      // the polling off the other waves' way
+      int jw = 0, kw = INT_MIN, bw = 0;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if (!((pend >> e) & 1)) continue;
-        const int u = ld_level(j[e]);
-        if (u >= 0) {
-          mx = u > mx ? u : mx;
-          pend &= ~(1 << e);
+        const int key = upper ? -j[e] : j[e];
+        const bool w = ((pend >> e) & 1) && key > kw;
+        jw = w ? j[e] : jw;
+        kw = w ? key : kw;
+        bw = w ? 1 << e : bw;
+      }
+      int u;
+      while ((u = ld_level(jw)) < 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (give_up(spins, err)) {
+          gave_up = true;
+          break;
         }
       }
+      mx = u > mx ? u : mx;
+      pend &= ~bw;
     }
     return mx;
   };

@@ -41,6 +41,9 @@ WORKLOADS = {
            "C=4, sweeps=5, tol 1e-10, seed 0",
     "semigauss": "dense semi-Gaussian 2000000x2000 float32 storage: columns 1000..1999 scaled 1e-4, 1% of rows "
                  "scaled 1e3; C=4, sweeps=5, tol 1e-10, seed 0",
+    "laplacian": "graph Laplacian, not grounded: incidence 1130067x2936 of two glued power-law random graphs "
+                 "(2000 vertices each, beta 5 / d 30 and beta 8 / d 10000, 5 shared, isolated vertices removed), "
+                 "+-1 values; float64; C=4, sweeps=5, tol 1e-10, seed 0",
 }
 
 

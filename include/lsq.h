@@ -98,7 +98,8 @@ typedef struct {
                           the dependency chain, older ones ahead of time on
                           other CUs (0: 48; at most 1024)                    */
   int32_t chain_levels; /* triangular solves: when x and the rows' partial sums
-                          fit in LDS and levels hold few rows (any rows when
+                          fit in LDS and levels hold at most 32 rows on
+                          average (any rows when
                           set explicitly), one wave sums
                           the entries reading rows at most this many levels
                           below (0: automatic, the most levels from 6 down to

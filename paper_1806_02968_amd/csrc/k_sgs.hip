@@ -1018,7 +1018,10 @@ int build_levels(lsq_ctx *ctx) {
     // and 4. Not below 3 while 8 entries per lane suffice: two consecutive
     // levels share a pass only from 3 levels on, and a solve in single-level
     // passes takes about 1.5 x as long)
-    const bool narrow = n <= 24 * (int64_t)std::min(Lf, Lb);
+    // (narrow: at most 2 passes of 16 rows per level on average; the 1.1M x
+    // 2936 graph Laplacian, 25 rows per level on average and up to 442, takes
+    // 87 us per solve in chain mode and 96 us in the one-workgroup form)
+    const bool narrow = n <= 32 * (int64_t)std::min(Lf, Lb);
     // an explicit depth takes chain mode also for wide levels
     if (kc > 0 && (narrow || ctx->opt.chain_levels > 0) && 2 * n * (int64_t)es <= 160 * 1024) K = kc;
   }

@@ -24,9 +24,10 @@ FAMILIES = {
     "gaussian_ragged": lambda: gaussian_dense(1237, 77, seed=3),
     "sparse_ragged": lambda: sparse_rowscaled(m=5003, n=131, k=7, seed=4),
     "semigauss_f64": lambda: semi_gaussian_dense(6001, 130, seed=5, dtype=np.float64),
+    "laplacian": lambda: make_config("laplacian", scale="small")[0],
 }
 SWEEPS = {"gaussian": 1, "sparse": 2, "graph": 5, "udv": 5, "semigauss": 5, "gaussian_ragged": 1,
-          "sparse_ragged": 3, "semigauss_f64": 2}
+          "sparse_ragged": 3, "semigauss_f64": 2, "laplacian": 5}
 # families whose condition number lets two correct solvers that both stop at
 # ||A^T r|| <= 1e-10 ||A^T b|| agree to 1e-9 in x (kappa(A^T A) * 1e-10 << 1e-9
 # after normalisation); the others are compared iterate by iterate and through
@@ -197,6 +198,29 @@ def test_backward_matches_oracle(case):
     gA_np = gA.cpu().numpy().reshape(gA_o.shape)
     tol = 1e-8 if p.dtype == np.float64 else 1e-5
     assert rel(gA_np, gA_o) <= tol
+
+
+def test_laplacian_full_size():
+    """Section 5.5's Laplacian workload at the bench size (1,130,067 x 2936,
+    singular normal equations): the GPU solve meets the stopping test in
+    float64, within one iteration of the oracle, with the same fitted values
+    A x (unique for any least-squares solution) and the same x up to the
+    conditioning of the stopping test."""
+    print("\n[laplacian] full size", flush=True)
+    p, cfg = make_config("laplacian")
+    s, _ = make_solver(p, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0)
+    x, info = s.solve()
+    o = oracle.Oracle(p, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0)
+    xo, io = o.solve(tol=1e-10)
+    x = x.cpu().numpy()
+    assert info["converged"] == 1 and info["relres_true"] <= 1e-10
+    assert abs(info["iters"] - io["iters"]) <= 1
+    rows = np.repeat(np.arange(p.m), 2)
+    Ad = np.bincount(rows, weights=p.values * (x - xo)[p.col_idx], minlength=p.m)
+    Ao = np.bincount(rows, weights=p.values * xo[p.col_idx], minlength=p.m)
+    assert np.linalg.norm(Ad) <= 1e-8 * np.linalg.norm(Ao)
+    xt, _ = o.solve(tol=1e-14, max_iter=20 * p.n)
+    assert rel(x, xo) <= 10 * max(rel(xo, xt), 1e-12)
 
 
 # ---------------------------------------------------------------------------

@@ -11,7 +11,7 @@ import pytest
 import scipy.linalg as sla
 
 import oracle
-from workloads import (coherent_identity, er_incidence, gaussian_dense, semi_coherent_block,
+from workloads import (coherent_identity, er_incidence, gaussian_dense, powerlaw_laplacian, semi_coherent_block,
                        sparse_rowscaled, make_config)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -496,3 +496,74 @@ def test_small_workloads_converge(name):
     o = oracle.Oracle(p, C_=cfg["C"], sweeps=cfg["sweeps"], seed=0)
     x, info = o.solve(tol=1e-10)
     assert info["status"] == 0 and info["relres_true"] <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Section 5.5's random graph Laplacian workload (singular normal equations)
+
+
+def _laplacian_table():
+    return [tuple(int(v) for v in r) for r in _read_table("graph_laplacian_table.txt")]
+
+
+def test_laplacian_table_is_simple_graph_incidence():
+    # every printed row has nnz(B^T B) = 2m + n: one row of B per distinct
+    # edge, no loops (the reading the generator follows)
+    for n, m, s, nnz in _laplacian_table():
+        assert nnz == 2 * m + n
+        assert oracle.sample_size(4.0, n) == s
+
+
+def test_laplacian_generator_structure():
+    import scipy.sparse as sp
+    for n0, seed in ((100, 0), (300, 3)):
+        p = powerlaw_laplacian(n0, seed=seed)
+        assert np.all(np.diff(p.row_ptr) == 2)
+        assert np.all(p.values[0::2] == 1.0) and np.all(p.values[1::2] == -1.0)
+        assert np.all(p.col_idx[0::2] < p.col_idx[1::2])
+        assert np.all(np.bincount(p.col_idx, minlength=p.n) > 0)  # no isolated vertex left
+        B = sp.csr_matrix((p.values, p.col_idx, p.row_ptr), shape=(p.m, p.n))
+        assert np.abs(B @ np.ones(p.n)).max() == 0.0  # constants span (part of) the null space
+        edges = set(zip(p.col_idx[0::2].tolist(), p.col_idx[1::2].tolist()))
+        assert (B.T @ B).nnz == 2 * len(edges) + p.n
+        # edge counts of the two graphs against the sum of the pair probabilities
+        for (beta, d), cnt in (((5.0, 30.0), p.meta["edges_sparse"]), ((8.0, 5.0 * n0), p.meta["edges_dense"])):
+            ex = -1.0 / (beta - 1.0)
+            w = (beta - 2.0) / (beta - 1.0) * d * n0 ** ex * np.arange(11, 11 + n0, dtype=np.float64) ** ex
+            P = np.minimum(1.0, np.outer(w, w) / w.sum())[np.triu_indices(n0, 1)]
+            assert abs(cnt - P.sum()) <= 6.0 * math.sqrt((P * (1.0 - P)).sum()) + 1e-9
+
+
+def test_laplacian_generator_sizes_match_the_table():
+    rows = _laplacian_table()
+    # the first row's size: 187 vertices and 5078 edges
+    for seed in (0, 1):
+        p = powerlaw_laplacian(100, seed=seed)
+        assert abs(p.n - 187) <= 6 and abs(p.m - 5078) <= 0.02 * 5078
+    # edge density m / n^2 of the other rows, at generator sizes near their n
+    for (n, m, _, _), n0 in zip(rows[1:], (185, 275, 365, 440)):
+        p = powerlaw_laplacian(n0, seed=0)
+        assert abs(p.m / p.n ** 2 - m / n ** 2) <= 0.1 * m / n ** 2
+
+
+def test_oracle_on_singular_laplacian():
+    """PCG on the consistent, singular normal equations of the Laplacian
+    workload: the stopping test is met, the fitted values A x equal those of
+    a library least-squares solution (they are unique), x differs from it by
+    a constant on each connected component, and the preconditioner cuts the
+    iteration count against CG (sweeps = 0), as in Section 5.5's table."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    p, cfg = make_config("laplacian", scale="small")
+    x, info = oracle.Oracle(p, C_=4.0, sweeps=cfg["sweeps"], seed=0).solve(tol=1e-10)
+    assert info["relres_true"] <= 1e-10
+    B = p.dense()
+    xl = np.linalg.lstsq(B, p.b, rcond=None)[0]
+    assert np.linalg.norm(B @ (x - xl)) <= 1e-8 * np.linalg.norm(B @ xl)
+    G = sp.coo_matrix((np.ones(p.m), (p.col_idx[0::2], p.col_idx[1::2])), shape=(p.n, p.n))
+    nc, lab = connected_components(G, directed=False)
+    for c in range(nc):
+        d = (x - xl)[lab == c]
+        assert np.ptp(d) <= 1e-7 * np.linalg.norm(xl)
+    _, icg = oracle.Oracle(p, C_=4.0, sweeps=0, seed=0).solve(tol=1e-10)
+    assert icg["relres_true"] <= 1e-10 and info["iters"] < icg["iters"]

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs shaped like the paper's five matrix families.
+"""Seeded synthetic inputs shaped like the paper's matrix families.
 
 This package only draws random matrices and right-hand sides. It holds none of
 the solver's arithmetic (no norms, no sampling, no Gram products, no solves),
@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     udv_dense,
     er_incidence,
     semi_gaussian_dense,
+    powerlaw_laplacian,
     coherent_identity,
     semi_coherent_block,
     make_config,

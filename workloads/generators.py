@@ -272,6 +272,70 @@ def er_incidence(nv: int, ne: int, seed: int = 0, noise: float = 1e-6, dtype=np.
     return _finish(p, noise, seed, with_target=True)
 
 
+def _chung_lu_edges(nv: int, beta: float, d: float, i0: int, g: np.random.Generator):
+    """Edges (i, j), i < j, of a random graph with expected degrees following a
+    power law (Section 5.5): w_i = c (i0 + i)^(-1/(beta-1)) for i = 0..nv-1,
+    c = (beta-2)/(beta-1) * d * nv^(-1/(beta-1)), and each pair joined with
+    probability min(1, w_i w_j / sum(w)). Pairs are drawn row by row of the
+    upper triangle, one uniform per pair."""
+    ex = -1.0 / (beta - 1.0)
+    c = (beta - 2.0) / (beta - 1.0) * d * float(nv) ** ex
+    w = c * np.arange(i0, i0 + nv, dtype=np.float64) ** ex
+    rho = 1.0 / w.sum()
+    us, vs = [], []
+    for i in range(nv - 1):
+        p = np.minimum(1.0, w[i] * w[i + 1:] * rho)
+        j = np.nonzero(g.random(nv - 1 - i) < p)[0] + (i + 1)
+        us.append(np.full(j.size, i, dtype=np.int64))
+        vs.append(j.astype(np.int64))
+    return np.concatenate(us), np.concatenate(vs)
+
+
+def powerlaw_laplacian(n0: int, seed: int = 0, noise: float = 1e-6, i0: int = 11, overlap: int = 5,
+                       sparse_graph=(5.0, 30.0), dense_graph=(8.0, None), dtype=np.float64) -> Problem:
+    """Incidence matrix of two glued power-law random graphs, not grounded
+    (Section 5.5's random graph Laplacian workload).
+
+    B1: a sparse, ill-conditioned graph on n0 vertices (beta = 5, average
+    degree parameter d = 30); B2: a dense, well-conditioned one on n0 vertices
+    (beta = 8, d = 5 n0); both with i0 = 11. B2's vertex k becomes vertex
+    n0 - overlap + k, so the two graphs share `overlap` vertices; B1's rows
+    come first, then B2's, each in (i, j) order, as (+1 at i, -1 at j).
+    Vertices without edges are removed (columns renumbered in order). No
+    column is dropped: A^T A is a graph Laplacian, singular with the constant
+    vectors of the connected components as its null space, and the least
+    squares problem is consistent in the normal equations.
+    """
+    b1, d1 = sparse_graph
+    b2, d2 = dense_graph
+    if d2 is None:
+        d2 = 5.0 * n0
+    u1, v1 = _chung_lu_edges(n0, b1, d1, i0, _rng(seed, _S_EDGES, 0))
+    u2, v2 = _chung_lu_edges(n0, b2, d2, i0, _rng(seed, _S_EDGES, 1))
+    shift = n0 - overlap
+    u = np.concatenate([u1, u2 + shift])
+    v = np.concatenate([v1, v2 + shift])
+    nv = 2 * n0 - overlap
+    used = np.zeros(nv, dtype=bool)
+    used[u] = True
+    used[v] = True
+    newid = np.cumsum(used) - 1
+    u, v = newid[u], newid[v]
+    n = int(used.sum())
+    m = int(u.size)
+    row_ptr = np.arange(0, 2 * m + 1, 2, dtype=np.int64)
+    col = np.empty(2 * m, dtype=np.int32)
+    val = np.empty(2 * m, dtype=np.float64)
+    col[0::2], col[1::2] = u, v
+    val[0::2], val[1::2] = 1.0, -1.0
+    x = _rng(seed, _S_XSTAR).standard_normal(n)
+    p = Problem("csr", m, n, b=None, x_star=x, row_ptr=row_ptr, col_idx=col, values=val.astype(dtype),
+                meta=dict(family="powerlaw_laplacian", n0=n0, seed=seed, noise=noise, i0=i0, overlap=overlap,
+                          sparse_graph=(b1, d1), dense_graph=(b2, d2), edges_sparse=int(u1.size),
+                          edges_dense=int(u2.size)))
+    return _finish(p, noise, seed, with_target=True)
+
+
 def semi_gaussian_dense(m: int, n: int, seed: int = 0, noise: float = 1e-6, small: float = 1e-4,
                         heavy_frac: float = 0.01, heavy_scale: float = 1e3, dtype=np.float32) -> Problem:
     """Column-scaled dense family with heavy rows (stands in for Section 5.2).
@@ -328,7 +392,7 @@ def semi_coherent_block(m: int, n: int, seed: int = 0) -> Problem:
 # named workloads
 
 
-CONFIG_NAMES = ("gaussian", "sparse", "udv", "graph", "semigauss")
+CONFIG_NAMES = ("gaussian", "sparse", "udv", "graph", "semigauss", "laplacian")
 
 # full sizes of the five workloads: (generator, kwargs, solver settings)
 _FULL = {
@@ -337,6 +401,7 @@ _FULL = {
     "udv": (udv_dense, dict(m=200_000, n=1000, noise=1e-8), dict(C=4.0, sweeps=5)),
     "graph": (er_incidence, dict(nv=100_000, ne=2_000_000, noise=1e-6), dict(C=4.0, sweeps=5)),
     "semigauss": (semi_gaussian_dense, dict(m=2_000_000, n=2000, noise=1e-6), dict(C=4.0, sweeps=5)),
+    "laplacian": (powerlaw_laplacian, dict(n0=2000, noise=1e-6), dict(C=4.0, sweeps=5)),
 }
 
 # reduced sizes with the same structure, for parity tests the oracle finishes in seconds
@@ -346,6 +411,7 @@ _SMALL = {
     "udv": dict(m=8000, n=160),
     "graph": dict(nv=3000, ne=30_000),
     "semigauss": dict(m=20_000, n=200),
+    "laplacian": dict(n0=100),
 }
 
 

@@ -187,6 +187,7 @@ struct lsq_ctx {
   double prof_bytes[kProfSlots] = {};
   int prof_used = 0;
   bool prof_ready = false;
+  hipEvent_t scal_ev = nullptr;  // marks the PCG scalars' copy to the host
   lsq_kernel_stats kstats{};
 
   lsq_info info{};
@@ -282,6 +283,7 @@ namespace lsq {
 int prof_begin(lsq_ctx *c, int cls);
 void prof_end(lsq_ctx *c, int slot, double bytes);
 void prof_harvest(lsq_ctx *c);  // call after the stream has been synchronised
+void prof_harvest_ready(lsq_ctx *c);  // harvests the launches already complete
 enum { KC_TRSV = LSQ_KC_TRSV, KC_SGS_RHS = LSQ_KC_SGS_RHS, KC_ATAP = LSQ_KC_ATAP, KC_VEC = LSQ_KC_VEC, KC_GRAM = LSQ_KC_GRAM };
 }  // namespace lsq
 

@@ -218,6 +218,22 @@ void prof_harvest(lsq_ctx *c) {
   }
   c->prof_used = 0;
 }
+void prof_harvest_ready(lsq_ctx *c) {
+  int done = 0;
+  while (done < c->prof_used && hipEventQuery(c->prof_ev[2 * done + 1]) == hipSuccess) ++done;
+  if (done == 0) return;
+  const int used = c->prof_used;
+  c->prof_used = done;
+  prof_harvest(c);
+  // the launches still running move to the front, with their events
+  for (int i = done; i < used; ++i) {
+    std::swap(c->prof_ev[2 * (i - done)], c->prof_ev[2 * i]);
+    std::swap(c->prof_ev[2 * (i - done) + 1], c->prof_ev[2 * i + 1]);
+    c->prof_cls[i - done] = c->prof_cls[i];
+    c->prof_bytes[i - done] = c->prof_bytes[i];
+  }
+  c->prof_used = used - done;
+}
 }  // namespace lsq
 
 extern "C" int lsq_get_kernel_stats(lsq_ctx *ctx, lsq_kernel_stats *stats, int32_t reset) {
@@ -298,6 +314,10 @@ extern "C" void lsq_destroy(lsq_ctx *ctx) {
   if (ctx->prof_ready) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int i = 0; i < 2 * lsq_ctx::kProfSlots; ++i) give_event(ctx->prof_ev[i]);
+  }
+  if (ctx->scal_ev) {
+    (void)hipStreamSynchronize(ctx->stream);
+    give_event(ctx->scal_ev);
   }
   (void)hipStreamSynchronize(ctx->stream);  // nothing queued still uses the blocks or the pinned scalars
   release_blocks(ctx->device, ctx->allocs);
@@ -590,13 +610,22 @@ struct Ops<float> {
   static float *q(lsq_ctx *c) { return c->fq; }
 };
 
+// PCG iterations from the current (y, r); the next iteration's
+// preconditioner application is queued ahead while the residual is above
+// kSpecMargin times the tolerance
+constexpr double kSpecMargin = 20.0;
+
 template <typename T>
 static int pcg_run(lsq_ctx *ctx, const double *dscale, double nf, double tol, int64_t max_iter, int64_t fixed,
                    int64_t *k, double *rel) {
   hipStream_t st = ctx->stream;
   const int64_t n = ctx->n;
   T *y = Ops<T>::y(ctx), *r = Ops<T>::r(ctx), *z = Ops<T>::z(ctx), *p = Ops<T>::p(ctx), *q = Ops<T>::q(ctx);
-  bool restart = true;
+  bool restart = true, have_z = false;
+  if (!ctx->scal_ev && take_event(&ctx->scal_ev) != hipSuccess) {
+    ctx->scal_ev = nullptr;
+    return END_ERROR;
+  }
   for (;;) {
     if (fixed >= 0) {
       if (*k >= fixed) return END_FIXED;
@@ -604,7 +633,8 @@ static int pcg_run(lsq_ctx *ctx, const double *dscale, double nf, double tol, in
       return END_CONVERGED;
     }
     if (*k >= max_iter) return END_MAXITER;
-    Ops<T>::P(ctx, r, z);
+    if (!have_z) Ops<T>::P(ctx, r, z);
+    have_z = false;
     int np = Vec<T>::dot_partials(n, r, z, nullptr, ctx->part, st);
     if (restart) {
       launch_finish(ctx->part, np, ctx->scal, 0, 2, st);
@@ -620,7 +650,22 @@ static int pcg_run(lsq_ctx *ctx, const double *dscale, double nf, double tol, in
     launch_finish(ctx->part, np, ctx->scal, 0, 1, st);
     np = Vec<T>::update_yr(n, ctx->scal + Scal::ALPHA, p, q, y, r, dscale, ctx->part, st);
     launch_finish(ctx->part, np, ctx->scal, Scal::RNORM2, 0, st);
-    if (read_scalars(ctx) != LSQ_OK) return END_ERROR;
+    // the scalars go to the host; unless this iteration may end the loop, the
+    // next iteration's P r (which needs only the new r) is queued before the
+    // host waits for them, so the GPU does not idle through the round trip.
+    // Unneeded only when the residual falls more than kSpecMargin-fold in one
+    // iteration; the arithmetic is the same either way
+    if (hipMemcpyAsync(ctx->hscal, ctx->scal, Scal::COUNT * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipEventRecord(ctx->scal_ev, st) != hipSuccess)
+      return END_ERROR;
+    const bool may_end = fixed >= 0 ? *k + 1 >= fixed : *rel <= kSpecMargin * tol;
+    if (!may_end && *k + 1 < max_iter) {
+      Ops<T>::P(ctx, r, z);
+      have_z = true;
+    }
+    if (hipEventSynchronize(ctx->scal_ev) != hipSuccess) return END_ERROR;
+    prof_harvest_ready(ctx);
     const double pq = ctx->hscal[Scal::PQ], rho = ctx->hscal[Scal::RHO];
     if (!(pq > 0.0) || !(rho > 0.0)) return END_BREAKDOWN;
     ++*k;

@@ -185,6 +185,7 @@ struct lsq_ctx {
   hipEvent_t prof_ev[2 * kProfSlots] = {};
   int prof_cls[kProfSlots] = {};
   double prof_bytes[kProfSlots] = {};
+  int prof_alias[kProfSlots] = {};  // >= 0: the slot starts at that event (a predecessor's end)
   int prof_used = 0;
   bool prof_ready = false;
   hipEvent_t scal_ev = nullptr;  // marks the PCG scalars' copy to the host
@@ -282,6 +283,9 @@ namespace lsq {
 // kernel timing around launches of one class; no-ops unless opt.profile
 int prof_begin(lsq_ctx *c, int cls);
 void prof_end(lsq_ctx *c, int slot, double bytes);
+// ends `slot` and begins a slot of class cls at the same event (for launches
+// queued back to back: one timing event between them instead of two)
+int prof_switch(lsq_ctx *c, int slot, double bytes, int cls);
 void prof_harvest(lsq_ctx *c);  // call after the stream has been synchronised
 void prof_harvest_ready(lsq_ctx *c);  // harvests the launches already complete
 enum { KC_TRSV = LSQ_KC_TRSV, KC_SGS_RHS = LSQ_KC_SGS_RHS, KC_ATAP = LSQ_KC_ATAP, KC_VEC = LSQ_KC_VEC, KC_GRAM = LSQ_KC_GRAM };

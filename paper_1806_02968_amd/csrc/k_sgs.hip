@@ -1402,25 +1402,22 @@ static void sgs_apply(lsq_ctx *c, const T *val, const T *r, T *z, T *tmp) {
     return;
   }
   const double tb = trsv_bytes<T>(c), rb = rhs_bytes<T>(c);
+  // the 4t - 1 launches run back to back: one timing event between two
   int slot = prof_begin(c, KC_TRSV);
   launch_trsv<T, false>(c, r, z);  // first forward step from e = 0
-  prof_end(c, slot, tb);
   for (int k = 1; k < t; ++k) {
-    slot = prof_begin(c, KC_SGS_RHS);
+    slot = prof_switch(c, slot, tb, KC_SGS_RHS);
     launch_rhs<T, true>(c, val, r, z, tmp);
-    prof_end(c, slot, rb);
-    slot = prof_begin(c, KC_TRSV);
+    slot = prof_switch(c, slot, rb, KC_TRSV);
     launch_trsv<T, false>(c, tmp, z);
-    prof_end(c, slot, tb);
   }
   for (int k = 0; k < t; ++k) {
-    slot = prof_begin(c, KC_SGS_RHS);
+    slot = prof_switch(c, slot, tb, KC_SGS_RHS);
     launch_rhs<T, false>(c, val, r, z, tmp);
-    prof_end(c, slot, rb);
-    slot = prof_begin(c, KC_TRSV);
+    slot = prof_switch(c, slot, rb, KC_TRSV);
     launch_trsv<T, true>(c, tmp, z);
-    prof_end(c, slot, tb);
   }
+  prof_end(c, slot, tb);
 }
 
 void sgs_apply_f64(lsq_ctx *c, const double *r, double *z) { sgs_apply<double>(c, c->Md, r, z, c->vrhs); }

@@ -199,8 +199,22 @@ int prof_begin(lsq_ctx *c, int cls) {
   }
   const int slot = c->prof_used++;
   c->prof_cls[slot] = cls;
+  c->prof_alias[slot] = -1;
   (void)hipEventRecord(c->prof_ev[2 * slot], c->stream);
   return slot;
+}
+int prof_switch(lsq_ctx *c, int slot, double bytes, int cls) {
+  if (slot < 0) return prof_begin(c, cls);
+  if (c->prof_used == lsq_ctx::kProfSlots) {
+    prof_end(c, slot, bytes);
+    return prof_begin(c, cls);
+  }
+  c->prof_bytes[slot] = bytes;
+  (void)hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
+  const int next = c->prof_used++;
+  c->prof_cls[next] = cls;
+  c->prof_alias[next] = 2 * slot + 1;
+  return next;
 }
 void prof_end(lsq_ctx *c, int slot, double bytes) {
   if (slot < 0) return;
@@ -210,7 +224,8 @@ void prof_end(lsq_ctx *c, int slot, double bytes) {
 void prof_harvest(lsq_ctx *c) {
   for (int i = 0; i < c->prof_used; ++i) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]) != hipSuccess) continue;
+    const hipEvent_t start = c->prof_alias[i] >= 0 ? c->prof_ev[c->prof_alias[i]] : c->prof_ev[2 * i];
+    if (hipEventElapsedTime(&ms, start, c->prof_ev[2 * i + 1]) != hipSuccess) continue;
     const int k = c->prof_cls[i];
     c->kstats.launches[k] += 1;
     c->kstats.ms[k] += ms;
@@ -221,6 +236,8 @@ void prof_harvest(lsq_ctx *c) {
 void prof_harvest_ready(lsq_ctx *c) {
   int done = 0;
   while (done < c->prof_used && hipEventQuery(c->prof_ev[2 * done + 1]) == hipSuccess) ++done;
+  // a remaining slot that starts at a harvested slot's end keeps that slot
+  while (done > 0 && done < c->prof_used && c->prof_alias[done] >= 0) --done;
   if (done == 0) return;
   const int used = c->prof_used;
   c->prof_used = done;
@@ -231,6 +248,7 @@ void prof_harvest_ready(lsq_ctx *c) {
     std::swap(c->prof_ev[2 * (i - done) + 1], c->prof_ev[2 * i + 1]);
     c->prof_cls[i - done] = c->prof_cls[i];
     c->prof_bytes[i - done] = c->prof_bytes[i];
+    c->prof_alias[i - done] = c->prof_alias[i] >= 0 ? c->prof_alias[i] - 2 * done : -1;
   }
   c->prof_used = used - done;
 }

@@ -814,28 +814,45 @@ __device__ __forceinline__ void row_bounds(bool upper, int n, int i, const int32
 // in chain mode), 0: near (up to D levels below), 2: far
 __device__ __forceinline__ int entry_class(int dl, int K, int D) { return dl <= K ? 1 : (dl <= D ? 0 : 2); }
 
+// entries of a row at level distance 1 .. kHistLevels (the candidates for the
+// automatic chain depth)
+constexpr int kHistLevels = 6;
+
+// cnt[i] = (near, late, far) entries of row i; with hist, also the entries at
+// each level distance 1 .. kHistLevels (hist[i * kHistLevels + d - 1])
 template <bool DENSE>
 __global__ __launch_bounds__(256) void k_split_count(int n, bool upper, int K, int D, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const int32_t *__restrict__ dg,
-                                                     const int32_t *__restrict__ lev, int4 *__restrict__ cnt) {
+                                                     const int32_t *__restrict__ lev, int4 *__restrict__ cnt,
+                                                     int32_t *__restrict__ hist) {
   const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x % kWave;
   if (i >= n) return;  // whole waves
   int64_t a, b;
   row_bounds<DENSE>(upper, n, i, rp, dg, &a, &b);
   const int li = lev[i];
-  int c0 = 0, c1 = 0, c2 = 0;
+  int c0 = 0, c1 = 0, c2 = 0, h[kHistLevels] = {};
   for (int64_t k = a + lane; k < b; k += kWave) {
     const int j = DENSE ? (int)(k - (int64_t)i * n) : ci[k];
-    const int cl = entry_class(li - lev[j], K, D);
+    const int dl = li - lev[j];
+    const int cl = entry_class(dl, K, D);
     c0 += cl == 0;
     c1 += cl == 1;
     c2 += cl == 2;
+#pragma unroll
+    for (int d = 0; d < kHistLevels; ++d) h[d] += dl == d + 1;
   }
   c0 = wave_sum(c0);
   c1 = wave_sum(c1);
   c2 = wave_sum(c2);
   if (lane == 0) cnt[i] = make_int4(c0, c1, c2, 0);
+  if (hist) {
+#pragma unroll
+    for (int d = 0; d < kHistLevels; ++d) {
+      const int t = wave_sum(h[d]);
+      if (lane == 0) hist[(int64_t)i * kHistLevels + d] = t;
+    }
+  }
 }
 
 // Copies row i's entries in task order: near then late entries at main
@@ -1031,30 +1048,75 @@ int build_levels(lsq_ctx *ctx) {
   const unsigned rows_grid = (unsigned)((n * kWave + 255) / 256);
   std::vector<int4> hcnt(2 * n);
   int32_t maxlate = 0;
-  for (;;) {
+  auto count = [&](int k, int32_t *hist) {
     for (int u = 0; u < 2; ++u) {
       const int32_t *lv = u ? dlev_b : dlev_f;
+      int32_t *hu = hist ? hist + u * n * kHistLevels : nullptr;
       if (dense)
-        k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, K, D, nullptr, nullptr, nullptr, lv,
-                                                       dcnt + u * n);
+        k_split_count<true><<<rows_grid, 256, 0, st>>>((int)n, u == 1, k, D, nullptr, nullptr, nullptr, lv,
+                                                       dcnt + u * n, hu);
       else
-        k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, K, D, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
-                                                        dcnt + u * n);
+        k_split_count<false><<<rows_grid, 256, 0, st>>>((int)n, u == 1, k, D, ctx->Mrp, ctx->Mci, ctx->Mdiag, lv,
+                                                        dcnt + u * n, hu);
     }
+  };
+  if (K > 1 && ctx->opt.chain_levels == 0 && K <= kHistLevels && D >= K) {
+    // automatic depth: one counting pass at K with the entries per level
+    // distance; the depth follows from those on the host, and the counts of
+    // the chosen depth are derived exactly (near + late does not depend on
+    // it), then formed once more on the device without a round trip
+    int32_t *dhist;
+    if ((rc = alloc(2 * n * kHistLevels * sizeof(int32_t), (void **)&dhist)) != LSQ_OK) return rc;
+    count(K, dhist);
     LSQ_HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> hh(2 * n * kHistLevels);
     LSQ_HIP_CHECK(hipMemcpyAsync(hcnt.data(), dcnt, 2 * n * sizeof(int4), hipMemcpyDeviceToHost, st));
+    LSQ_HIP_CHECK(hipMemcpyAsync(hh.data(), dhist, hh.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LSQ_HIP_CHECK(hipStreamSynchronize(st));
-    maxlate = 0;
-    for (int64_t i = 0; i < 2 * n; ++i) maxlate = std::max(maxlate, hcnt[i].y);
+    auto late = [&](int64_t i, int k) {
+      int32_t t = 0;
+      for (int d = 0; d < k; ++d) t += hh[i * kHistLevels + d];
+      return t;
+    };
+    auto max_late = [&](int k) {
+      int32_t mx = 0;
+      for (int64_t i = 0; i < 2 * n; ++i) mx = std::max(mx, late(i, k));
+      return mx;
+    };
+    const int K0 = K;
     // the chain holds at most 8 entries per lane
-    if (K == 1) break;
-    if (ctx->opt.chain_levels == 0 &&
-        ((maxlate > kChainLanes * 2 && K > 3) || (maxlate > kChainLanes * 8 && K > 2))) {
-      --K;
-      continue;
+    for (;;) {
+      maxlate = max_late(K);
+      if (K == 1) break;
+      if ((maxlate > kChainLanes * 2 && K > 3) || (maxlate > kChainLanes * 8 && K > 2)) {
+        --K;
+        continue;
+      }
+      if (maxlate <= kChainLanes * 8) break;
+      K = 1;
     }
-    if (maxlate <= kChainLanes * 8) break;
-    K = 1;
+    if (K != K0) {
+      for (int64_t i = 0; i < 2 * n; ++i) {
+        const int32_t y = late(i, K);
+        hcnt[i].x += hcnt[i].y - y;
+        hcnt[i].y = y;
+      }
+      count(K, nullptr);
+      LSQ_HIP_CHECK(hipGetLastError());
+    }
+    lsq_free_one(ctx, dhist);
+  } else {
+    for (;;) {
+      count(K, nullptr);
+      LSQ_HIP_CHECK(hipGetLastError());
+      LSQ_HIP_CHECK(hipMemcpyAsync(hcnt.data(), dcnt, 2 * n * sizeof(int4), hipMemcpyDeviceToHost, st));
+      LSQ_HIP_CHECK(hipStreamSynchronize(st));
+      maxlate = 0;
+      for (int64_t i = 0; i < 2 * n; ++i) maxlate = std::max(maxlate, hcnt[i].y);
+      // the chain holds at most 8 entries per lane
+      if (K == 1 || maxlate <= kChainLanes * 8) break;
+      K = 1;
+    }
   }
   const bool chain = K > 1;
   int ec = 2;

@@ -146,6 +146,7 @@ struct lsq_ctx {
   int G = 64;  // lanes per row in the strict-part products
   int trsv_e = 4;  // near entries per lane of the triangular solves' main block
   bool trsv_chain = false;  // chain mode of the triangular solves
+  bool trsv_preset = false;  // the next solve's sentinel slots were set by the kernel before it
   int trsv_ec = 2;          // chain entries per lane (chain mode)
   TriDev tri_f, tri_b;
   void *tdg = nullptr;     // diagonal of M
@@ -158,9 +159,9 @@ struct lsq_ctx {
 
   // work vectors
   double *vy = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr, *vu = nullptr,
-         *vg = nullptr, *vrhs = nullptr, *vx = nullptr;
+         *vg = nullptr, *vrhs = nullptr, *vx = nullptr, *vz2 = nullptr;
   float *fy = nullptr, *fr = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr, *fu = nullptr,
-        *frhs = nullptr, *fe = nullptr;
+        *frhs = nullptr, *fe = nullptr, *fz2 = nullptr;
   double *part = nullptr;  // reduction partials / dense A^T(Ap) partial rows
   size_t part_bytes = 0;
   double *scal = nullptr;  // device scalars (float64)

@@ -577,11 +577,22 @@ __global__ __launch_bounds__(256) void k_trsv_reset(int n, T *__restrict__ x, in
 }
 
 // out_i = r_i - sum over the strict upper (UPPER_PART) or strict lower part of
-// row i of M_ij e_j
+// row i of M_ij e_j. With sx, also sets the sentinel slots of the solve that
+// follows (its n x slots in sx, not e, and nslot far-sum slots), in place of
+// a k_trsv_reset launch.
 template <typename T, bool DENSE, bool UPPER_PART, int G>
 __global__ __launch_bounds__(256) void k_sgs_rhs(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                  const T *__restrict__ val, const int32_t *__restrict__ dg,
-                                                 const T *__restrict__ r, const T *__restrict__ e, T *__restrict__ out) {
+                                                 const T *__restrict__ r, const T *__restrict__ e, T *__restrict__ out,
+                                                 T *__restrict__ sx, int nslot, T *__restrict__ sfar) {
+  if (sx) {
+    typedef typename Bits<T>::U U;
+    const int64_t m = n > nslot ? n : nslot;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x) {
+      if (q < n) ((U *)sx)[q] = Bits<T>::kSent;
+      if (q < nslot) ((U *)sfar)[q] = Bits<T>::kSent;
+    }
+  }
   const int gl = threadIdx.x % G;
   const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
@@ -1301,8 +1312,9 @@ static void launch_trsv_x(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
     attr_set = true;
   }
   const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
-  k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
-                                                                          (T *)c->farbuf);
+  if (!c->trsv_preset)
+    k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
+                                                                            (T *)c->farbuf);
   const int helpers =
       (int)std::min<int64_t>(std::min(kMaxHelpers, c->ncu - 1), (d.nft + kTrsvWaves - 1) / kTrsvWaves);
   // x in global memory: enough main blocks that each wave holds about half
@@ -1359,8 +1371,9 @@ static void launch_trsv_chain(lsq_ctx *c, const TriDev &d, const T *rhs, T *x) {
     attr_set = true;
   }
   const int64_t nreset = std::max<int64_t>(c->n, d.nslot);
-  k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
-                                                                          (T *)c->farbuf);
+  if (!c->trsv_preset)
+    k_trsv_reset<T><<<(unsigned)((nreset + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, (int)d.nslot,
+                                                                            (T *)c->farbuf);
   constexpr int hwaves = chain_threads(E, EC) / kWave;
   const int helpers =
       (int)std::min<int64_t>(std::min(kMaxChainHelpers, c->ncu - 1), (d.nft + hwaves - 1) / hwaves);
@@ -1420,22 +1433,27 @@ static void launch_trsv(lsq_ctx *c, const T *rhs, T *x) {
 }
 
 template <typename T, bool UPPER_PART>
-static void launch_rhs(lsq_ctx *c, const T *val, const T *r, const T *e, T *out) {
+static void launch_rhs(lsq_ctx *c, const T *val, const T *r, const T *e, T *out, T *sx, int nslot) {
   const int64_t n = c->n;
   int64_t b = (n * (c->Mdense ? 64 : c->G) + 255) / 256;
   if (b < 1) b = 1;
   if (b > 8192) b = 8192;
+  T *sf = (T *)c->farbuf;
+#define LSQ_RHS(DD, GG)                                                                                         \
+  k_sgs_rhs<T, DD, UPPER_PART, GG><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, \
+                                                                      out, sx, nslot, sf)
   if (c->Mdense) {
-    k_sgs_rhs<T, true, UPPER_PART, 64><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out);
+    LSQ_RHS(true, 64);
     return;
   }
   switch (c->G) {
-    case 4: k_sgs_rhs<T, false, UPPER_PART, 4><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out); break;
-    case 8: k_sgs_rhs<T, false, UPPER_PART, 8><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out); break;
-    case 16: k_sgs_rhs<T, false, UPPER_PART, 16><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out); break;
-    case 32: k_sgs_rhs<T, false, UPPER_PART, 32><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out); break;
-    default: k_sgs_rhs<T, false, UPPER_PART, 64><<<(unsigned)b, 256, 0, c->stream>>>((int)n, c->Mrp, c->Mci, val, c->Mdiag, r, e, out); break;
+    case 4: LSQ_RHS(false, 4); break;
+    case 8: LSQ_RHS(false, 8); break;
+    case 16: LSQ_RHS(false, 16); break;
+    case 32: LSQ_RHS(false, 32); break;
+    default: LSQ_RHS(false, 64); break;
   }
+#undef LSQ_RHS
 }
 
 // algorithmic bytes of one triangular solve and of one strict-part product:
@@ -1456,33 +1474,42 @@ static double rhs_bytes(const lsq_ctx *c) {
   return strict * (sizeof(T) + 4) + n * (8 + 3 * sizeof(T));
 }
 
+// The 2t solves write their iterate alternately into z2 and z (the last one
+// into z), so that the strict-part product before a solve, which reads the
+// previous iterate, can also set the sentinel slots of the next one.
 template <typename T>
-static void sgs_apply(lsq_ctx *c, const T *val, const T *r, T *z, T *tmp) {
+static void sgs_apply(lsq_ctx *c, const T *val, const T *r, T *z, T *tmp, T *z2) {
   const int t = c->sweeps;
   if (t == 0) {
     Vec<T>::copy(c->n, r, z, c->stream);
     return;
   }
+  auto target = [&](int s) { return (2 * t - 1 - s) % 2 == 0 ? z : z2; };
   const double tb = trsv_bytes<T>(c), rb = rhs_bytes<T>(c);
   // the 4t - 1 launches run back to back: one timing event between two
   int slot = prof_begin(c, KC_TRSV);
-  launch_trsv<T, false>(c, r, z);  // first forward step from e = 0
-  for (int k = 1; k < t; ++k) {
+  launch_trsv<T, false>(c, r, target(0));  // first forward step from e = 0
+  int s = 1;
+  for (int k = 1; k < t; ++k, ++s) {
     slot = prof_switch(c, slot, tb, KC_SGS_RHS);
-    launch_rhs<T, true>(c, val, r, z, tmp);
+    launch_rhs<T, true>(c, val, r, target(s - 1), tmp, target(s), (int)c->tri_f.nslot);
     slot = prof_switch(c, slot, rb, KC_TRSV);
-    launch_trsv<T, false>(c, tmp, z);
+    c->trsv_preset = true;
+    launch_trsv<T, false>(c, tmp, target(s));
+    c->trsv_preset = false;
   }
-  for (int k = 0; k < t; ++k) {
+  for (int k = 0; k < t; ++k, ++s) {
     slot = prof_switch(c, slot, tb, KC_SGS_RHS);
-    launch_rhs<T, false>(c, val, r, z, tmp);
+    launch_rhs<T, false>(c, val, r, target(s - 1), tmp, target(s), (int)c->tri_b.nslot);
     slot = prof_switch(c, slot, rb, KC_TRSV);
-    launch_trsv<T, true>(c, tmp, z);
+    c->trsv_preset = true;
+    launch_trsv<T, true>(c, tmp, target(s));
+    c->trsv_preset = false;
   }
   prof_end(c, slot, tb);
 }
 
-void sgs_apply_f64(lsq_ctx *c, const double *r, double *z) { sgs_apply<double>(c, c->Md, r, z, c->vrhs); }
-void sgs_apply_f32(lsq_ctx *c, const float *r, float *z) { sgs_apply<float>(c, c->Mf, r, z, c->frhs); }
+void sgs_apply_f64(lsq_ctx *c, const double *r, double *z) { sgs_apply<double>(c, c->Md, r, z, c->vrhs, c->vz2); }
+void sgs_apply_f32(lsq_ctx *c, const float *r, float *z) { sgs_apply<float>(c, c->Mf, r, z, c->frhs, c->fz2); }
 
 }  // namespace lsq

@@ -514,6 +514,7 @@ static int setup_impl(lsq_ctx *ctx) {
   ALLOC(ctx->vg, double, n);
   ALLOC(ctx->vrhs, double, n);
   ALLOC(ctx->vx, double, n);
+  ALLOC(ctx->vz2, double, n);
   if (fp32) {
     ALLOC(ctx->fy, float, n);
     ALLOC(ctx->fr, float, n);
@@ -522,6 +523,7 @@ static int setup_impl(lsq_ctx *ctx) {
     ALLOC(ctx->fq, float, n);
     ALLOC(ctx->fu, float, n);
     ALLOC(ctx->frhs, float, n);
+    ALLOC(ctx->fz2, float, n);
   }
   LSQ_HIP_CHECK(hipMemcpyAsync(hflags, ctx->flags, sizeof(hflags), hipMemcpyDeviceToHost, st));
   LSQ_HIP_CHECK(hipStreamSynchronize(st));

@@ -223,6 +223,34 @@ def test_laplacian_full_size():
     assert rel(x, xo) <= 10 * max(rel(xo, xt), 1e-12)
 
 
+@pytest.mark.parametrize("name", ["sparse", "laplacian", "gaussian"])
+def test_kernel_timing_accounts_for_every_launch(name):
+    """With kernel timing on, every preconditioner application is counted:
+    2t triangular solves and 2t - 1 right-hand sides per PCG iteration (one
+    more application when the one queued ahead of the convergence test was
+    not needed), each timed launch with a positive duration and the
+    algorithmic bytes of its class, and the timed total within the solve's
+    wall time. A repeated solve agrees to rounding (the sparse A^T(Ap) kernels
+    with atomics sum in scheduling order)."""
+    import torch
+    p = FAMILIES[name]()
+    t = SWEEPS[name]
+    print("\n[timing] %s" % name, flush=True)
+    s, _ = make_solver(p, C_=4.0, sweeps=t, seed=0, profile=True)
+    s.kernel_stats(reset=True)
+    x1, info = s.solve()
+    ks = s.kernel_stats(reset=True)
+    k = info["iters"]
+    apps = ks["trsv"]["launches"] // (2 * t)
+    assert ks["trsv"]["launches"] == apps * 2 * t and apps in (k, k + 1)
+    assert ks["sgs_rhs"]["launches"] == apps * (2 * t - 1)
+    for c in ("trsv", "sgs_rhs"):
+        assert ks[c]["ms"] > 0 and ks[c]["bytes"] > 0
+    assert ks["trsv"]["ms"] + ks["sgs_rhs"]["ms"] <= info["solve_ms"] * 1.05
+    x2, _ = s.solve()
+    assert rel(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-12
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 

@@ -263,13 +263,14 @@ struct Vec {
                        const double *d, double *part, hipStream_t st);
   // p = z + beta p  (beta == null: p = z)
   static void update_p(int64_t n, const double *beta, const T *z, T *p, hipStream_t st);
+  // the same, also writing u = s .* p (the scaled input of the operator product)
+  static void update_p_scaled(int64_t n, const double *beta, const T *z, T *p, const T *s, T *u, hipStream_t st);
 };
 // single-block finisher over `np` partials (fixed order, deterministic):
 // op 0: scal[dst] = sum; op 1: scal[PQ] = sum, scal[ALPHA] = scal[RHO] / sum;
-// op 2: scal[RHO] = scal[RHO_NEW] = sum
+// op 2: scal[RHO] = scal[RHO_NEW] = sum; op 3: scal[RHO_NEW] = sum,
+// scal[BETA] = sum / scal[RHO], scal[RHO] = sum
 void launch_finish(const double *part, int np, double *scal, int dst, int op, hipStream_t st);
-// beta = scal[RHO_NEW] / scal[RHO]; scal[RHO] = scal[RHO_NEW]
-void launch_beta(double *scal, hipStream_t st);
 // x = a .* y in float64 (x = D^-1 y) and float32->float64 axpy helpers
 void launch_axpy_scaled_f64(int64_t n, double nu, const double *invD, const float *d, double *x,
                             hipStream_t st);

@@ -683,7 +683,7 @@ static void atap_dense_t(lsq_ctx *c, const TA *A, const CT *u, const double *b, 
 }
 
 template <typename TA, typename CT, bool HAS_B, int G>
-static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, bool lds) {
+static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT *q, bool lds, const CT *s_out) {
   const int64_t m = c->m;
   const int n = (int)c->n;
   hipStream_t st = c->stream;
@@ -711,7 +711,7 @@ static void atap_csr_g(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
     CT *part2 = part + nblk * (int64_t)n;
     const int64_t fb = (n + 255) / 256;
     k_part_reduce<CT><<<dim3((unsigned)(fb > 0 ? fb : 1), (unsigned)nseg), 256, 0, st>>>(n, part, (int)nblk, seg, part2);
-    k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part2, nseg, nullptr, q);
+    k_atap_finish<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(n, part2, nseg, s_out, q);
   } else {
     const int64_t rows_per_blk_iter = (kAtThreads / G) * csr_unroll<G>();
     int64_t nblk = (m + rows_per_blk_iter - 1) / rows_per_blk_iter;
@@ -765,13 +765,15 @@ static void atap_csr_t(lsq_ctx *c, const TA *v, const CT *u, const double *b, CT
     else launch_fill_f32((float *)q, c->n, 0.0f, st);
   }
   const double avg = (double)c->nnz / (double)c->m;
-  if (avg <= 2) atap_csr_g<TA, CT, HAS_B, 2>(c, v, u, b, q, lds);
-  else if (avg <= 4) atap_csr_g<TA, CT, HAS_B, 4>(c, v, u, b, q, lds);
-  else if (avg <= 8) atap_csr_g<TA, CT, HAS_B, 8>(c, v, u, b, q, lds);
-  else if (avg <= 16) atap_csr_g<TA, CT, HAS_B, 16>(c, v, u, b, q, lds);
-  else if (avg <= 32) atap_csr_g<TA, CT, HAS_B, 32>(c, v, u, b, q, lds);
-  else atap_csr_g<TA, CT, HAS_B, 64>(c, v, u, b, q, lds);
-  if (s_out) {
+  // the LDS form scales its output in the finishing pass
+  const CT *fs = lds ? s_out : nullptr;
+  if (avg <= 2) atap_csr_g<TA, CT, HAS_B, 2>(c, v, u, b, q, lds, fs);
+  else if (avg <= 4) atap_csr_g<TA, CT, HAS_B, 4>(c, v, u, b, q, lds, fs);
+  else if (avg <= 8) atap_csr_g<TA, CT, HAS_B, 8>(c, v, u, b, q, lds, fs);
+  else if (avg <= 16) atap_csr_g<TA, CT, HAS_B, 16>(c, v, u, b, q, lds, fs);
+  else if (avg <= 32) atap_csr_g<TA, CT, HAS_B, 32>(c, v, u, b, q, lds, fs);
+  else atap_csr_g<TA, CT, HAS_B, 64>(c, v, u, b, q, lds, fs);
+  if (s_out && !lds) {
     int64_t fb = (c->n + 255) / 256;
     k_scale_inplace<CT><<<(unsigned)(fb > 0 ? fb : 1), 256, 0, st>>>(c->n, s_out, q);
   }

@@ -76,6 +76,19 @@ __global__ void k_update_p(int64_t n, const double *__restrict__ beta, const T *
     p[i] = beta ? z[i] + bt * p[i] : z[i];
 }
 
+// p = z + beta p (p = z without beta) and u = s p, the scaled input of the
+// next operator product
+template <typename T>
+__global__ void k_update_p_scaled(int64_t n, const double *__restrict__ beta, const T *__restrict__ z,
+                                  T *__restrict__ p, const T *__restrict__ s, T *__restrict__ u) {
+  const T bt = beta ? (T)(*beta) : (T)0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T pi = beta ? z[i] + bt * p[i] : z[i];
+    p[i] = pi;
+    u[i] = s[i] * pi;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part, int np, double *scal, int dst,
                                                 int op) {
   __shared__ double red[256 / kWave];
@@ -88,17 +101,14 @@ __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part,
     } else if (op == 1) {  // p.q -> alpha = rho / (p.q)
       scal[Scal::PQ] = acc;
       scal[Scal::ALPHA] = scal[Scal::RHO] / acc;
-    } else {  // r.z at a (re)start: rho = rho_new = r.z
+    } else if (op == 2) {  // r.z at a (re)start: rho = rho_new = r.z
       scal[Scal::RHO] = acc;
       scal[Scal::RHO_NEW] = acc;
+    } else {  // r.z in a later iteration: beta = rho_new / rho, then rho = rho_new
+      scal[Scal::RHO_NEW] = acc;
+      scal[Scal::BETA] = acc / scal[Scal::RHO];
+      scal[Scal::RHO] = acc;
     }
-  }
-}
-
-__global__ void k_beta(double *scal) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    scal[Scal::BETA] = scal[Scal::RHO_NEW] / scal[Scal::RHO];
-    scal[Scal::RHO] = scal[Scal::RHO_NEW];
   }
 }
 
@@ -157,13 +167,17 @@ void Vec<T>::update_p(int64_t n, const double *beta, const T *z, T *p, hipStream
   k_update_p<T><<<grid_for(n), kVecThreads, 0, st>>>(n, beta, z, p);
 }
 
+template <typename T>
+void Vec<T>::update_p_scaled(int64_t n, const double *beta, const T *z, T *p, const T *s, T *u, hipStream_t st) {
+  k_update_p_scaled<T><<<grid_for(n), kVecThreads, 0, st>>>(n, beta, z, p, s, u);
+}
+
 template struct Vec<double>;
 template struct Vec<float>;
 
 void launch_finish(const double *part, int np, double *scal, int dst, int op, hipStream_t st) {
   k_finish<<<1, 256, 0, st>>>(part, np, scal, dst, op);
 }
-void launch_beta(double *scal, hipStream_t st) { k_beta<<<1, 64, 0, st>>>(scal); }
 void launch_axpy_scaled_f64(int64_t n, double nu, const double *invD, const float *d, double *x, hipStream_t st) {
   k_axpy_scaled<<<grid_for(n), kVecThreads, 0, st>>>(n, nu, invD, d, x);
 }

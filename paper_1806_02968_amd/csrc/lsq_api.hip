@@ -613,6 +613,10 @@ template <>
 struct Ops<double> {
   static void P(lsq_ctx *c, const double *r, double *z) { sgs_apply_f64(c, r, z); }
   static void K(lsq_ctx *c, const double *p, double *q) { atap_f64(c, c->invD, p, nullptr, q, c->invD); }
+  // K from an input already scaled by invD (u = invD p)
+  static void K_pre(lsq_ctx *c, const double *u, double *q) { atap_f64(c, nullptr, u, nullptr, q, c->invD); }
+  static const double *s(lsq_ctx *c) { return c->invD; }
+  static double *u(lsq_ctx *c) { return c->vu; }
   static double *y(lsq_ctx *c) { return c->vy; }
   static double *r(lsq_ctx *c) { return c->vr; }
   static double *z(lsq_ctx *c) { return c->vz; }
@@ -623,6 +627,9 @@ template <>
 struct Ops<float> {
   static void P(lsq_ctx *c, const float *r, float *z) { sgs_apply_f32(c, r, z); }
   static void K(lsq_ctx *c, const float *p, float *q) { atap_f32(c, c->invD32, p, q, c->invD32); }
+  static void K_pre(lsq_ctx *c, const float *u, float *q) { atap_f32(c, nullptr, u, q, c->invD32); }
+  static const float *s(lsq_ctx *c) { return c->invD32; }
+  static float *u(lsq_ctx *c) { return c->fu; }
   static float *y(lsq_ctx *c) { return c->fy; }
   static float *r(lsq_ctx *c) { return c->fr; }
   static float *z(lsq_ctx *c) { return c->fz; }
@@ -656,16 +663,17 @@ static int pcg_run(lsq_ctx *ctx, const double *dscale, double nf, double tol, in
     if (!have_z) Ops<T>::P(ctx, r, z);
     have_z = false;
     int np = Vec<T>::dot_partials(n, r, z, nullptr, ctx->part, st);
+    // p = z + beta p, with the operator's scaled input u = invD p in the same pass
+    T *u = Ops<T>::u(ctx);
     if (restart) {
       launch_finish(ctx->part, np, ctx->scal, 0, 2, st);
-      Vec<T>::update_p(n, nullptr, z, p, st);
+      Vec<T>::update_p_scaled(n, nullptr, z, p, Ops<T>::s(ctx), u, st);
       restart = false;
     } else {
-      launch_finish(ctx->part, np, ctx->scal, Scal::RHO_NEW, 0, st);
-      launch_beta(ctx->scal, st);
-      Vec<T>::update_p(n, ctx->scal + Scal::BETA, z, p, st);
+      launch_finish(ctx->part, np, ctx->scal, Scal::RHO_NEW, 3, st);
+      Vec<T>::update_p_scaled(n, ctx->scal + Scal::BETA, z, p, Ops<T>::s(ctx), u, st);
     }
-    Ops<T>::K(ctx, p, q);
+    Ops<T>::K_pre(ctx, u, q);
     np = Vec<T>::dot_partials(n, p, q, nullptr, ctx->part, st);
     launch_finish(ctx->part, np, ctx->scal, 0, 1, st);
     np = Vec<T>::update_yr(n, ctx->scal + Scal::ALPHA, p, q, y, r, dscale, ctx->part, st);

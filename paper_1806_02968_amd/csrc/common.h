@@ -251,16 +251,26 @@ void resid64(lsq_ctx *c, const double *x, const double *b, double *g);
 void grad_pass(lsq_ctx *c, const double *x, const double *lam, double *grad_b, void *grad_A);
 
 // vector ops (k_vec.hip)
+// a reduction finished in the kernel that forms its partials: scal[dst] and
+// the op of launch_finish; cnt counts the workgroups that have arrived (zero
+// between reductions)
+struct Fin {
+  double *scal;
+  int dst, op;
+  unsigned *cnt;
+};
+
 template <typename T>
 struct Vec {
   static void scale(int64_t n, const T *a, const T *x, T *y, hipStream_t st);  // y = a.*x
   static void copy(int64_t n, const T *x, T *y, hipStream_t st);
-  // dot partials: part[nb] = partial sums of x.*y (or (d.*x)^2 when d != null and y == null)
+  // dot partials: part[nb] = partial sums of x.*y (or (d.*x)^2 when d != null and y == null);
+  // with fin, the last workgroup also finishes the sum (launch_finish's op)
   static int dot_partials(int64_t n, const T *x, const T *y, const double *d, double *part,
-                          hipStream_t st);
+                          hipStream_t st, const Fin *fin = nullptr);
   // y += alpha p; r -= alpha q; partial sums of (d .* r)^2 (d may be null)
   static int update_yr(int64_t n, const double *alpha, const T *p, const T *q, T *y, T *r,
-                       const double *d, double *part, hipStream_t st);
+                       const double *d, double *part, hipStream_t st, const Fin *fin = nullptr);
   // p = z + beta p  (beta == null: p = z)
   static void update_p(int64_t n, const double *beta, const T *z, T *p, hipStream_t st);
   // the same, also writing u = s .* p (the scaled input of the operator product)

@@ -28,12 +28,54 @@ __global__ void k_copy(int64_t n, const T *__restrict__ x, T *__restrict__ y) {
     y[i] = x[i];
 }
 
+__device__ __forceinline__ void finish_op(double *scal, int dst, int op, double acc) {
+  {
+    if (op == 0) {
+      scal[dst] = acc;
+    } else if (op == 1) {  // p.q -> alpha = rho / (p.q)
+      scal[Scal::PQ] = acc;
+      scal[Scal::ALPHA] = scal[Scal::RHO] / acc;
+    } else if (op == 2) {  // r.z at a (re)start: rho = rho_new = r.z
+      scal[Scal::RHO] = acc;
+      scal[Scal::RHO_NEW] = acc;
+    } else {  // r.z in a later iteration: beta = rho_new / rho, then rho = rho_new
+      scal[Scal::RHO_NEW] = acc;
+      scal[Scal::BETA] = acc / scal[Scal::RHO];
+      scal[Scal::RHO] = acc;
+    }
+  }
+}
+
+// after part[blockIdx.x] is written: the last workgroup to arrive sums the
+// partials exactly as k_finish does (same thread layout and order) and
+// applies the op, then clears the count for the next reduction
+__device__ __forceinline__ void finish_if_last(const double *part, const Fin &fin) {
+  __shared__ double red[kVecThreads / kWave];
+  __shared__ bool last;
+  __syncthreads();  // thread 0 has written this workgroup's partial
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(fin.cnt, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    acc += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    finish_op(fin.scal, fin.dst, fin.op, acc);
+    __hip_atomic_store(fin.cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // partial sums of x.*y, or of (d.*x)^2 when y is null
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_dot_part(int64_t n, const T *__restrict__ x,
                                                           const T *__restrict__ y,
                                                           const double *__restrict__ d,
-                                                          double *__restrict__ part) {
+                                                          double *__restrict__ part, Fin fin) {
   __shared__ T red[kVecThreads / kWave];
   T acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -46,6 +88,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dot_part(int64_t n, const T *__
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = (double)acc;
+  if (fin.cnt) finish_if_last(part, fin);
 }
 
 template <typename T>
@@ -53,7 +96,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_yr(int64_t n, const doub
                                                            const T *__restrict__ p, const T *__restrict__ q,
                                                            T *__restrict__ y, T *__restrict__ r,
                                                            const double *__restrict__ d,
-                                                           double *__restrict__ part) {
+                                                           double *__restrict__ part, Fin fin) {
   __shared__ T red[kVecThreads / kWave];
   const T a = (T)(*alpha);
   T acc = 0;
@@ -66,6 +109,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_yr(int64_t n, const doub
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = (double)acc;
+  if (fin.cnt) finish_if_last(part, fin);
 }
 
 template <typename T>
@@ -95,22 +139,9 @@ __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part,
   double acc = 0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) {
-    if (op == 0) {
-      scal[dst] = acc;
-    } else if (op == 1) {  // p.q -> alpha = rho / (p.q)
-      scal[Scal::PQ] = acc;
-      scal[Scal::ALPHA] = scal[Scal::RHO] / acc;
-    } else if (op == 2) {  // r.z at a (re)start: rho = rho_new = r.z
-      scal[Scal::RHO] = acc;
-      scal[Scal::RHO_NEW] = acc;
-    } else {  // r.z in a later iteration: beta = rho_new / rho, then rho = rho_new
-      scal[Scal::RHO_NEW] = acc;
-      scal[Scal::BETA] = acc / scal[Scal::RHO];
-      scal[Scal::RHO] = acc;
-    }
-  }
+  if (threadIdx.x == 0) finish_op(scal, dst, op, acc);
 }
+
 
 __global__ void k_axpy_scaled(int64_t n, double nu, const double *__restrict__ invD, const float *__restrict__ d,
                               double *__restrict__ x) {
@@ -150,16 +181,17 @@ void Vec<T>::copy(int64_t n, const T *x, T *y, hipStream_t st) {
   k_copy<T><<<grid_for(n), kVecThreads, 0, st>>>(n, x, y);
 }
 template <typename T>
-int Vec<T>::dot_partials(int64_t n, const T *x, const T *y, const double *d, double *part, hipStream_t st) {
+int Vec<T>::dot_partials(int64_t n, const T *x, const T *y, const double *d, double *part, hipStream_t st,
+                         const Fin *fin) {
   int nb = vec_blocks(n);
-  k_dot_part<T><<<nb, kVecThreads, 0, st>>>(n, x, y, d, part);
+  k_dot_part<T><<<nb, kVecThreads, 0, st>>>(n, x, y, d, part, fin ? *fin : Fin{});
   return nb;
 }
 template <typename T>
 int Vec<T>::update_yr(int64_t n, const double *alpha, const T *p, const T *q, T *y, T *r, const double *d,
-                      double *part, hipStream_t st) {
+                      double *part, hipStream_t st, const Fin *fin) {
   int nb = vec_blocks(n);
-  k_update_yr<T><<<nb, kVecThreads, 0, st>>>(n, alpha, p, q, y, r, d, part);
+  k_update_yr<T><<<nb, kVecThreads, 0, st>>>(n, alpha, p, q, y, r, d, part, fin ? *fin : Fin{});
   return nb;
 }
 template <typename T>

@@ -358,7 +358,7 @@ static int setup_impl(lsq_ctx *ctx) {
   const int64_t m = ctx->m, n = ctx->n;
   const bool fp32 = ctx->opt.mode == LSQ_MODE_FP32_REFINE;
 
-  ALLOC(ctx->flags, int32_t, 8);
+  ALLOC(ctx->flags, int32_t, 16);  // [8]: arrival count of the fused reductions
   ALLOC(ctx->scal, double, Scal::COUNT);
   ctx->hscal = take_pinned(Scal::COUNT);
   if (!ctx->hscal) RET(LSQ_ENOMEM);
@@ -381,7 +381,7 @@ static int setup_impl(lsq_ctx *ctx) {
   ALLOC(ctx->part, double, part_elems);
   ctx->part_bytes = part_elems * sizeof(double);
   if (ctx->fmt == LSQ_DENSE && n > 2048) ALLOC(ctx->vm, double, m);
-  launch_fill_i32(ctx->flags, 8, 0, st);
+  launch_fill_i32(ctx->flags, 16, 0, st);
 
   // argument checks that need the device; nothing indexes with A's column
   // indices before they have been validated
@@ -662,22 +662,19 @@ static int pcg_run(lsq_ctx *ctx, const double *dscale, double nf, double tol, in
     if (*k >= max_iter) return END_MAXITER;
     if (!have_z) Ops<T>::P(ctx, r, z);
     have_z = false;
-    int np = Vec<T>::dot_partials(n, r, z, nullptr, ctx->part, st);
+    // reductions finish in their own last workgroup (fixed order); the count
+    // of arrived workgroups lives in flags[8]
+    const Fin fin_rz{ctx->scal, restart ? 0 : Scal::RHO_NEW, restart ? 2 : 3, (unsigned *)(ctx->flags + 8)};
+    Vec<T>::dot_partials(n, r, z, nullptr, ctx->part, st, &fin_rz);
     // p = z + beta p, with the operator's scaled input u = invD p in the same pass
     T *u = Ops<T>::u(ctx);
-    if (restart) {
-      launch_finish(ctx->part, np, ctx->scal, 0, 2, st);
-      Vec<T>::update_p_scaled(n, nullptr, z, p, Ops<T>::s(ctx), u, st);
-      restart = false;
-    } else {
-      launch_finish(ctx->part, np, ctx->scal, Scal::RHO_NEW, 3, st);
-      Vec<T>::update_p_scaled(n, ctx->scal + Scal::BETA, z, p, Ops<T>::s(ctx), u, st);
-    }
+    Vec<T>::update_p_scaled(n, restart ? nullptr : ctx->scal + Scal::BETA, z, p, Ops<T>::s(ctx), u, st);
+    restart = false;
     Ops<T>::K_pre(ctx, u, q);
-    np = Vec<T>::dot_partials(n, p, q, nullptr, ctx->part, st);
-    launch_finish(ctx->part, np, ctx->scal, 0, 1, st);
-    np = Vec<T>::update_yr(n, ctx->scal + Scal::ALPHA, p, q, y, r, dscale, ctx->part, st);
-    launch_finish(ctx->part, np, ctx->scal, Scal::RNORM2, 0, st);
+    const Fin fin_pq{ctx->scal, 0, 1, (unsigned *)(ctx->flags + 8)};
+    Vec<T>::dot_partials(n, p, q, nullptr, ctx->part, st, &fin_pq);
+    const Fin fin_rn{ctx->scal, Scal::RNORM2, 0, (unsigned *)(ctx->flags + 8)};
+    Vec<T>::update_yr(n, ctx->scal + Scal::ALPHA, p, q, y, r, dscale, ctx->part, st, &fin_rn);
     // the scalars go to the host; unless this iteration may end the loop, the
     // next iteration's P r (which needs only the new r) is queued before the
     // host waits for them, so the GPU does not idle through the round trip.

@@ -3,6 +3,7 @@
 // draws of Algorithm 1 from a Philox4x64-10 counter generator, and the
 // compaction of the drawn rows into (row, multiplicity) pairs.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -62,6 +63,63 @@ __global__ __launch_bounds__(256) void k_colnorm_dense(int64_t m, int64_t n, int
   }
 }
 
+// 16-byte loads for rows whose length and stride are multiples of a vector:
+// thread t owns the column vectors t, t + 256, ..., NC of them, and requests
+// RB rows of them before adding any (clamped row index; the row loop bound is
+// uniform). Each column still adds its rows in ascending order.
+template <typename TA>
+using Vec16 = typename std::conditional<sizeof(TA) == 4, float4, double2>::type;
+
+template <typename TA, int NC>
+__global__ __launch_bounds__(256) void k_colnorm_dense_vec(int64_t m, int64_t n, int64_t ld,
+                                                           const TA *__restrict__ A, double *__restrict__ part,
+                                                           int64_t rows_per_blk) {
+  constexpr int V = 16 / sizeof(TA), RB = 4;
+  typedef Vec16<TA> VT;
+  const int64_t r0 = blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < m ? r0 + rows_per_blk : m;
+  const int64_t nv = n / V;
+  int64_t gi[NC];
+  double acc[NC][V];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t g = threadIdx.x + 256 * c;
+    gi[c] = g < nv ? g : 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[c][k] = 0.0;
+  }
+  for (int64_t i0 = r0; i0 < r1; i0 += RB) {
+    VT x[RB][NC];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int64_t i = i0 + r < r1 ? i0 + r : r1 - 1;
+      const VT *row = (const VT *)(A + i * ld);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) x[r][c] = row[gi[c]];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (i0 + r >= r1) break;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const TA *e = (const TA *)&x[r][c];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const double a = (double)e[k];
+          acc[c][k] += a * a;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t g = threadIdx.x + 256 * c;
+    if (g < nv)
+#pragma unroll
+      for (int k = 0; k < V; ++k) part[blockIdx.x * n + g * V + k] = acc[c][k];
+  }
+}
+
 template <typename TA>
 __global__ void k_colnorm_csr(int64_t nnz, const int32_t *__restrict__ ci, const TA *__restrict__ v,
                               double *__restrict__ sumsq) {
@@ -86,12 +144,32 @@ __global__ void k_colnorm_finish(int64_t n, const double *__restrict__ part, int
   }
 }
 
+template <typename TA>
+static bool vec16_ok(const lsq_ctx *c) {
+  constexpr int V = 16 / sizeof(TA);
+  return c->n % V == 0 && c->ld % V == 0 && ((uintptr_t)c->A % 16) == 0;
+}
+
+template <typename TA>
+static void colnorm_dense_t(const lsq_ctx *c, double *part, int nblk, int64_t rpb, hipStream_t st) {
+  constexpr int V = 16 / sizeof(TA);
+  const TA *A = (const TA *)c->A;
+  const int64_t nc = (c->n / V + 255) / 256;
+  if (vec16_ok<TA>(c) && nc <= 8) {
+    // 2 million x 2000 float32: 7.35 ms with one 4-byte load per column and row
+    if (nc <= 1) k_colnorm_dense_vec<TA, 1><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, A, part, rpb);
+    else if (nc <= 2) k_colnorm_dense_vec<TA, 2><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, A, part, rpb);
+    else if (nc <= 4) k_colnorm_dense_vec<TA, 4><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, A, part, rpb);
+    else k_colnorm_dense_vec<TA, 8><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, A, part, rpb);
+    return;
+  }
+  k_colnorm_dense<TA><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, A, part, rpb);
+}
+
 void launch_colnorm_dense(const lsq_ctx *c, double *part, int nblk, hipStream_t st) {
   int64_t rpb = (c->m + nblk - 1) / nblk;
-  if (c->dtype == LSQ_F64)
-    k_colnorm_dense<double><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, (const double *)c->A, part, rpb);
-  else
-    k_colnorm_dense<float><<<nblk, 256, 0, st>>>(c->m, c->n, c->ld, (const float *)c->A, part, rpb);
+  if (c->dtype == LSQ_F64) colnorm_dense_t<double>(c, part, nblk, rpb, st);
+  else colnorm_dense_t<float>(c, part, nblk, rpb, st);
 }
 
 // column sums of squares of a CSR A into per-workgroup partial rows: block b
@@ -177,6 +255,61 @@ __global__ __launch_bounds__(256) void k_rowweight_dense(int64_t m, int64_t n, i
   }
 }
 
+// one wave per pair of rows with 16-byte loads, U vectors per lane per row
+// requested before any is used (clamped indices)
+template <typename TA>
+__global__ __launch_bounds__(256) void k_rowweight_dense_vec(int64_t m, int64_t n, int64_t ld,
+                                                             const TA *__restrict__ A,
+                                                             const double *__restrict__ invD, double *__restrict__ w,
+                                                             int32_t *flags) {
+  constexpr int V = 16 / sizeof(TA), RW = 2, U = 2;
+  typedef Vec16<TA> VT;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nv = n / V;
+  for (int64_t i0 = wave * RW; i0 < m; i0 += nwaves * RW) {
+    double acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
+    for (int64_t g0 = 0; g0 < nv; g0 += 64 * U) {
+      VT x[RW][U];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int64_t i = i0 + r < m ? i0 + r : m - 1;
+        const VT *row = (const VT *)(A + i * ld);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t g = g0 + lane + 64 * u;
+          x[r][u] = row[g < nv ? g : 0];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t g = g0 + lane + 64 * u;
+        if (g >= nv) continue;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const double d = invD[g * V + k];
+#pragma unroll
+          for (int r = 0; r < RW; ++r) {
+            const double a = (double)((const TA *)&x[r][u])[k] * d;
+            acc[r] += a * a;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const double t = wave_sum(acc[r]);
+      if (lane == 0 && i0 + r < m) {
+        w[i0 + r] = t;
+        if (!isfinite(t)) atomicOr(&flags[0], 2);
+      }
+    }
+  }
+}
+
 template <typename TA, int G>
 __global__ __launch_bounds__(256) void k_rowweight_csr(int64_t m, const int64_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const TA *__restrict__ v,
@@ -220,10 +353,20 @@ static void rowweight_csr_dispatch(const lsq_ctx *c, double *w, int32_t *flags, 
 void launch_rowweight(const lsq_ctx *c, double *w, int32_t *flags, hipStream_t st) {
   if (c->fmt == LSQ_DENSE) {
     unsigned grid = grid256(c->m * 64, 16384);
-    if (c->dtype == LSQ_F64)
-      k_rowweight_dense<double><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const double *)c->A, c->invD, w, flags);
-    else
-      k_rowweight_dense<float><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const float *)c->A, c->invD, w, flags);
+    if (c->dtype == LSQ_F64) {
+      if (vec16_ok<double>(c))
+        k_rowweight_dense_vec<double><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const double *)c->A, c->invD, w,
+                                                             flags);
+      else
+        k_rowweight_dense<double><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const double *)c->A, c->invD, w, flags);
+    } else {
+      // 2 million x 2000 float32: 4.6 ms with 4-byte loads
+      if (vec16_ok<float>(c))
+        k_rowweight_dense_vec<float><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const float *)c->A, c->invD, w,
+                                                            flags);
+      else
+        k_rowweight_dense<float><<<grid, 256, 0, st>>>(c->m, c->n, c->ld, (const float *)c->A, c->invD, w, flags);
+    }
   } else {
     if (c->dtype == LSQ_F64) rowweight_csr_dispatch<double>(c, w, flags, st);
     else rowweight_csr_dispatch<float>(c, w, flags, st);

@@ -226,8 +226,13 @@ size_t scan_scratch_elems(int64_t m);
 // M = As^T As (upper tiles by MFMA, mirrored)
 void launch_gather_dense_f64(const lsq_ctx *c, double *As, hipStream_t st);
 void launch_gather_dense_f32(const lsq_ctx *c, float *As, hipStream_t st);
-void launch_syrk_f64(int64_t sd, int64_t n, const double *As, double *M, hipStream_t st);
-void launch_syrk_f32(int64_t sd, int64_t n, const float *As, float *M, hipStream_t st);
+// M = A_s^T A_s on MFMA; nsplit > 1 splits the sampled rows, with a scratch
+// of syrk_scratch_elems(n, nsplit) values for the partial tiles
+int syrk_splits(int64_t sd, int64_t n, int ncu);
+size_t syrk_scratch_elems(int64_t n, int nsplit);
+void launch_syrk_f64(int64_t sd, int64_t n, const double *As, double *M, int nsplit, double *part,
+                     hipStream_t st);
+void launch_syrk_f32(int64_t sd, int64_t n, const float *As, float *M, int nsplit, float *part, hipStream_t st);
 void launch_dense_diag_guard_f64(int64_t n, double *M, int32_t *flags, hipStream_t st);
 void launch_dense_diag_guard_f32(int64_t n, float *M, int32_t *flags, hipStream_t st);
 // sparse Gram (several passes with host-read sizes); returns LSQ code

@@ -74,7 +74,7 @@ void launch_gather_dense_f32(const lsq_ctx *c, float *As, hipStream_t st) {
 // A[l%16][l/16] and B[l/16][l%16]; its four results are column l%16 of rows
 // l/16 + 4i (float64) or 4(l/16) + i (float32), i < 4.
 
-constexpr int kTile = 64, kKc = 16;
+constexpr int kTile = 64, kKc = 32;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -99,20 +99,37 @@ struct Acc4<float> {
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// tile index -> (tj, tl), tj <= tl, upper tiles in row order
+__device__ __forceinline__ void syrk_tile(int b, int nt, int *tj, int *tl) {
+  int t = 0;
+  while (b >= nt - t) {
+    b -= nt - t;
+    ++t;
+  }
+  *tj = t;
+  *tl = t + b;
+}
+
+// One 64 x 64 upper tile of A_s^T A_s per workgroup (4 waves, 32 x 32 each,
+// 2 x 2 MFMA 16 x 16 blocks), over the sampled rows of its split: kKc rows
+// per stage through LDS, the next stage's rows requested into registers
+// before the current stage's products (clamped indices, zeroed when stored).
+// With one split the tile is written to both triangles of M; with several,
+// each split writes its partial tile and k_syrk_reduce adds them in split
+// order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(int64_t sd, int64_t n, const T *__restrict__ As, T *__restrict__ M,
-                                              int nt) {
+                                              int nt, int64_t chunk, T *__restrict__ part) {
   typedef typename Acc4<T>::type acc_t;
+  constexpr int PER = kKc * kTile / 256;
   __shared__ T sj[kKc][kTile];
   __shared__ T sl[kKc][kTile];
-  // blockIdx -> (tj, tl) with tj <= tl
-  int b = blockIdx.x, tj = 0;
-  while (b >= nt - tj) {
-    b -= nt - tj;
-    ++tj;
-  }
-  const int tl = tj + b;
+  const int ntiles = nt * (nt + 1) / 2;
+  const int tile = blockIdx.x % ntiles, split = blockIdx.x / ntiles;
+  int tj, tl;
+  syrk_tile(tile, nt, &tj, &tl);
   const int64_t J0 = (int64_t)tj * kTile, L0 = (int64_t)tl * kTile;
+  const int64_t rb = split * chunk, re = rb + chunk < sd ? rb + chunk : sd;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wj = wv >> 1, wl = wv & 1;
   acc_t acc[2][2];
@@ -120,19 +137,32 @@ __global__ __launch_bounds__(256) void k_syrk(int64_t sd, int64_t n, const T *__
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
-
-  for (int64_t r0 = 0; r0 < sd; r0 += kKc) {
-    __syncthreads();
+  T rj[PER], rl[PER];
+  auto fetch = [&](int64_t r0) {
 #pragma unroll
-    for (int q = 0; q < (kKc * kTile) / 256; ++q) {
-      int e = threadIdx.x + q * 256;
-      int rr = e / kTile, cc = e % kTile;
-      int64_t r = r0 + rr;
-      int64_t jj = J0 + cc, ll = L0 + cc;
-      sj[rr][cc] = (r < sd && jj < n) ? As[r * n + jj] : (T)0;
-      sl[rr][cc] = (r < sd && ll < n) ? As[r * n + ll] : (T)0;
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int64_t r = r0 + e / kTile;
+      const int cc = e % kTile;
+      const int64_t rr = r < re ? r : rb;
+      const int64_t jj = J0 + cc < n ? J0 + cc : 0, ll = L0 + cc < n ? L0 + cc : 0;
+      rj[q] = As[rr * n + jj];
+      rl[q] = As[rr * n + ll];
+    }
+  };
+  if (rb < re) fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += kKc) {
+    __syncthreads();  // the previous stage's products are done with LDS
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int rr = e / kTile, cc = e % kTile;
+      const bool okr = r0 + rr < re;
+      sj[rr][cc] = okr && J0 + cc < n ? rj[q] : (T)0;
+      sl[rr][cc] = okr && L0 + cc < n ? rl[q] : (T)0;
     }
     __syncthreads();
+    if (r0 + kKc < re) fetch(r0 + kKc);
 #pragma unroll
     for (int ks = 0; ks < kKc / 4; ++ks) {
       const int kr = ks * 4 + (lane >> 4);
@@ -152,23 +182,71 @@ __global__ __launch_bounds__(256) void k_syrk(int64_t sd, int64_t n, const T *__
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int64_t j = J0 + wj * 32 + x * 16 + Acc4<T>::row(lane, i);
-        int64_t l = L0 + wl * 32 + y * 16 + (lane & 15);
-        if (j < n && l < n && l >= j) {
-          T v = acc[x][y][i];
-          M[j * n + l] = v;
-          M[l * n + j] = v;
+        const int jl = wj * 32 + x * 16 + Acc4<T>::row(lane, i);
+        const int ll = wl * 32 + y * 16 + (lane & 15);
+        const T v = acc[x][y][i];
+        if (part) {
+          part[((int64_t)split * ntiles + tile) * (kTile * kTile) + jl * kTile + ll] = v;
+        } else {
+          const int64_t j = J0 + jl, l = L0 + ll;
+          if (j < n && l < n && l >= j) {
+            M[j * n + l] = v;
+            M[l * n + j] = v;
+          }
         }
       }
 }
 
-void launch_syrk_f64(int64_t sd, int64_t n, const double *As, double *M, hipStream_t st) {
-  int nt = (int)((n + kTile - 1) / kTile);
-  k_syrk<double><<<nt * (nt + 1) / 2, 256, 0, st>>>(sd, n, As, M, nt);
+// M from the splits' partial tiles, added in split order (one workgroup per tile)
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_reduce(int64_t n, int nt, int nsplit, const T *__restrict__ part,
+                                                     T *__restrict__ M) {
+  const int ntiles = nt * (nt + 1) / 2, tile = blockIdx.x;
+  int tj, tl;
+  syrk_tile(tile, nt, &tj, &tl);
+  const int64_t J0 = (int64_t)tj * kTile, L0 = (int64_t)tl * kTile;
+  for (int loc = threadIdx.x; loc < kTile * kTile; loc += 256) {
+    const int64_t j = J0 + loc / kTile, l = L0 + loc % kTile;
+    if (j >= n || l >= n || l < j) continue;
+    T v = part[(int64_t)tile * (kTile * kTile) + loc];
+    for (int s = 1; s < nsplit; ++s) v += part[((int64_t)s * ntiles + tile) * (kTile * kTile) + loc];
+    M[j * n + l] = v;
+    M[l * n + j] = v;
+  }
 }
-void launch_syrk_f32(int64_t sd, int64_t n, const float *As, float *M, hipStream_t st) {
-  int nt = (int)((n + kTile - 1) / kTile);
-  k_syrk<float><<<nt * (nt + 1) / 2, 256, 0, st>>>(sd, n, As, M, nt);
+
+// splits of the sampled rows so that the launch has about two workgroups per
+// CU (n = 1000: 136 tiles), each split at least 8 stages long
+int syrk_splits(int64_t sd, int64_t n, int ncu) {
+  const int64_t nt = (n + kTile - 1) / kTile, ntiles = nt * (nt + 1) / 2;
+  int64_t S = (2 * (int64_t)std::max(ncu, 1) + ntiles - 1) / ntiles;
+  S = std::max<int64_t>(1, std::min<int64_t>({S, 8, sd / (8 * kKc)}));
+  return (int)S;
+}
+size_t syrk_scratch_elems(int64_t n, int nsplit) {
+  if (nsplit <= 1) return 0;
+  const int64_t nt = (n + kTile - 1) / kTile;
+  return (size_t)nsplit * (size_t)(nt * (nt + 1) / 2) * kTile * kTile;
+}
+
+template <typename T>
+static void launch_syrk_t(int64_t sd, int64_t n, const T *As, T *M, int nsplit, T *part, hipStream_t st) {
+  const int nt = (int)((n + kTile - 1) / kTile), ntiles = nt * (nt + 1) / 2;
+  if (nsplit <= 1 || !part) {
+    k_syrk<T><<<ntiles, 256, 0, st>>>(sd, n, As, M, nt, std::max<int64_t>(sd, 1), nullptr);
+    return;
+  }
+  int64_t chunk = (sd + nsplit - 1) / nsplit;
+  chunk = (chunk + kKc - 1) / kKc * kKc;
+  k_syrk<T><<<ntiles * nsplit, 256, 0, st>>>(sd, n, As, M, nt, chunk, part);
+  k_syrk_reduce<T><<<ntiles, 256, 0, st>>>(n, nt, nsplit, part, M);
+}
+void launch_syrk_f64(int64_t sd, int64_t n, const double *As, double *M, int nsplit, double *part,
+                     hipStream_t st) {
+  launch_syrk_t<double>(sd, n, As, M, nsplit, part, st);
+}
+void launch_syrk_f32(int64_t sd, int64_t n, const float *As, float *M, int nsplit, float *part, hipStream_t st) {
+  launch_syrk_t<float>(sd, n, As, M, nsplit, part, st);
 }
 
 template <typename T>

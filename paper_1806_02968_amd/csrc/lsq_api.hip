@@ -461,22 +461,30 @@ static int setup_impl(lsq_ctx *ctx) {
       ALLOC(As, float, std::max<int64_t>(ctx->s_d, 1) * n);
       ALLOC(ctx->Mf, float, n * n);
       launch_gather_dense_f32(ctx, As, st);
+      const int ns = syrk_splits(ctx->s_d, n, ctx->ncu);
+      float *sp = nullptr;
+      if (ns > 1) ALLOC(sp, float, syrk_scratch_elems(n, ns));
       const int gslot = prof_begin(ctx, KC_GRAM);
-      launch_syrk_f32(ctx->s_d, n, As, ctx->Mf, st);
+      launch_syrk_f32(ctx->s_d, n, As, ctx->Mf, ns, sp, st);
       prof_end(ctx, gslot, (double)ctx->s_d * (double)n * (double)(n + 1));
       launch_dense_diag_guard_f32(n, ctx->Mf, ctx->flags, st);
       LSQ_HIP_CHECK(hipStreamSynchronize(st));
+      if (sp) lsq_free_one(ctx, sp);
       lsq_free_one(ctx, As);
     } else {
       double *As;
       ALLOC(As, double, std::max<int64_t>(ctx->s_d, 1) * n);
       ALLOC(ctx->Md, double, n * n);
       launch_gather_dense_f64(ctx, As, st);
+      const int ns = syrk_splits(ctx->s_d, n, ctx->ncu);
+      double *sp = nullptr;
+      if (ns > 1) ALLOC(sp, double, syrk_scratch_elems(n, ns));
       const int gslot = prof_begin(ctx, KC_GRAM);
-      launch_syrk_f64(ctx->s_d, n, As, ctx->Md, st);
+      launch_syrk_f64(ctx->s_d, n, As, ctx->Md, ns, sp, st);
       prof_end(ctx, gslot, (double)ctx->s_d * (double)n * (double)(n + 1));
       launch_dense_diag_guard_f64(n, ctx->Md, ctx->flags, st);
       LSQ_HIP_CHECK(hipStreamSynchronize(st));
+      if (sp) lsq_free_one(ctx, sp);
       lsq_free_one(ctx, As);
     }
   } else {

@@ -29,7 +29,8 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32_refine": 157.3}  # dense matrix-core pea
 # commands. Only figures taken on the kernel code of this revision are listed.
 MEASURED_TRAFFIC = {("sparse", "k_trsv_chain"): 58.88e6}
 # triangular-solve kernel by lsq_info.trsv_mode
-TRSV_KERNEL = {0: "k_trsv (x in LDS)", 1: "k_trsv_chain", 2: "k_trsv (x in global memory)"}
+TRSV_KERNEL = {0: "k_trsv (x in LDS)", 1: "k_trsv_chain", 2: "k_trsv (x in global memory)",
+               3: "k_trsv_dense_blk"}
 
 WORKLOADS = {
     "sparse": "sparse CSR 1000000x10000, 10 nnz/row at uniform distinct columns, N(0,1) values, "

@@ -132,7 +132,8 @@ typedef struct {
   int32_t status;       /* return code of the last call                       */
   int32_t trsv_mode;    /* triangular solves: 0 one main workgroup with x in
                            LDS, 1 chain mode, 2 main workgroups with x in
-                           global memory                                      */
+                           global memory, 3 dense M in 64-row blocks, one
+                           workgroup per block                                */
   int32_t atap_algo;    /* sparse A: the A^T(Ap) kernel in use (values of
                            lsq_options.atap_algo); dense A: the option as
                            given (0: chosen per call by the vector length)    */

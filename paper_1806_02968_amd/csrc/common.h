@@ -135,6 +135,7 @@ struct lsq_ctx {
 
   // M: dense (n*n row-major) or CSR with int32 offsets
   bool Mdense = false;
+  bool dense_blk = false;  // dense M: blocked triangular solves
   int64_t nnzM = 0;
   double *Md = nullptr;   // float64 values (dense n*n or CSR nnz)
   float *Mf = nullptr;    // float32 values (FP32_REFINE)

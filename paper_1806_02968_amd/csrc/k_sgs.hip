@@ -66,6 +66,7 @@ constexpr int kMaxHelpers = 32;
 // while the registers allow it (up to 4 chain entries and 4 near entries per
 // lane), else 512 (1M x 10k sparse: 396 against 411 us per solve).
 constexpr int kChainLanes = 4, kChainRows = kWave / kChainLanes;
+constexpr int kDB = 64;  // rows per block of the blocked dense solve
 constexpr int chain_threads(int e, int ec) { return ec <= 4 && e <= 4 ? 1024 : 512; }
 constexpr int kMaxChainHelpers = 64;
 constexpr int kSpinLimit = 1 << 22;
@@ -1137,6 +1138,13 @@ int build_levels(lsq_ctx *ctx) {
   ctx->info.trsv_mode = chain ? 1 : (n * (int64_t)es <= 150 * 1024 ? 0 : 2);
   ctx->info.chain_levels = chain ? K : 0;
   ctx->info.chain_max = chain ? maxlate : 0;
+  // dense M: the blocked solve takes over whenever its row blocks fit one per CU
+  ctx->dense_blk = dense && (n + kDB - 1) / kDB <= ctx->ncu;
+  if (ctx->dense_blk) {
+    ctx->info.trsv_mode = 3;
+    ctx->info.chain_levels = 0;
+    ctx->info.chain_max = 0;
+  }
   constexpr int R = kMainR;
   bool too_big = false;
   int32_t maxnear = 0;
@@ -1411,8 +1419,112 @@ static void launch_trsv_chain_e(lsq_ctx *c, const TriDev &d, const T *rhs, T *x)
   }
 }
 
+// Dense M: blocked triangular solve. Workgroup b owns rows [64 b, 64 b + 64)
+// of the solve order's blocks; it adds the products with the off-diagonal
+// blocks in solve order as their x arrives (its block of M is requested into
+// registers one block ahead), then one wave solves the diagonal block: lane r
+// holds row r's remaining sum, each step broadcasts x_i with readlane and the
+// later rows subtract M_ri x_i. x slots hold the sentinel until written (set
+// before the launch) and are polled lane by lane; x is published with
+// agent-scope stores. Thread (r, q) = (t / 4, t % 4) multiplies 16 columns of
+// row r; the four parts are added at the end, so every sum has a fixed order.
+__device__ __forceinline__ double readlane_d(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane_d(float v, int i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(256) void k_trsv_dense_blk(int n, const T *__restrict__ Mv, const T *__restrict__ rhs,
+                                                        T *__restrict__ x, int32_t *__restrict__ err) {
+  typedef typename Bits<T>::U U;
+  __shared__ T dblk[kDB][kDB + 1];
+  __shared__ T xs[kDB];
+  __shared__ T bsh[kDB];
+  const int nb = (n + kDB - 1) / kDB;
+  const int jb = blockIdx.x;
+  const int j0 = jb * kDB, jn = min(kDB, n - j0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r = tid >> 2, q = tid & 3;
+  for (int e = tid; e < kDB * kDB; e += 256) {
+    const int rr = e / kDB, cc = e % kDB;
+    dblk[rr][cc] = rr < jn && cc < jn ? Mv[(int64_t)(j0 + rr) * n + j0 + cc] : (T)0;
+  }
+  const int kcount = UPPER ? nb - 1 - jb : jb;
+  auto kblk = [&](int t) { return UPPER ? nb - 1 - t : t; };
+  const int64_t row = j0 + r < n ? j0 + r : n - 1;
+  T m[16], mn[16];
+  auto loadm = [&](int kb, T (&dst)[16]) {
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int col = kb * kDB + q * 16 + cc;
+      dst[cc] = Mv[row * n + (col < n ? col : n - 1)];
+    }
+  };
+  T acc = 0;
+  if (kcount > 0) loadm(kblk(0), mn);
+  for (int t = 0; t < kcount; ++t) {
+    const int kb = kblk(t);
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) m[cc] = mn[cc];
+    if (t + 1 < kcount) loadm(kblk(t + 1), mn);
+    if (tid < kDB) {
+      const int col = kb * kDB + tid;
+      U xu = 0;
+      if (col < n) {
+        int spins = 0;
+        while ((xu = ld_sync(x + col)) == Bits<T>::kSent) {
+          __builtin_amdgcn_s_sleep(1);
+          if (give_up(spins, err)) {
+            xu = 0;
+            break;
+          }
+        }
+      }
+      xs[tid] = __builtin_bit_cast(T, xu);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) acc += m[cc] * xs[q * 16 + cc];
+    __syncthreads();  // xs is rewritten for the next block
+  }
+  acc = dpp_group_sum<4>(acc);
+  if (q == 0 && r < jn) bsh[r] = rhs[j0 + r] - acc;
+  __syncthreads();
+  if (tid < kWave) {
+    T b = lane < jn ? bsh[lane] : (T)0;
+    const T inv = lane < jn ? (T)1 / dblk[lane][lane] : (T)0;
+    T xv = 0;
+    for (int s = 0; s < jn; ++s) {
+      const int i = UPPER ? jn - 1 - s : s;
+      const T xi = readlane_d(b * inv, i);
+      xv = lane == i ? xi : xv;
+      const bool dep = UPPER ? lane < i : (lane > i && lane < jn);
+      const T mri = dblk[lane][i];
+      b = dep ? b - mri * xi : b;
+    }
+    if (lane < jn) st_sync(x + j0 + lane, xv);
+  }
+}
+
+template <typename T, bool UPPER>
+static bool launch_trsv_dense_blk(lsq_ctx *c, const T *rhs, T *x) {
+  const int64_t nb = (c->n + kDB - 1) / kDB;
+  if (!c->dense_blk || nb > c->ncu) return false;
+  const T *Mv = sizeof(T) == 8 ? (const T *)(const void *)c->Md : (const T *)(const void *)c->Mf;
+  if (!Mv) return false;
+  if (!c->trsv_preset)  // x slots to the sentinel (no far-sum slots here)
+    k_trsv_reset<T><<<(unsigned)((c->n + 255) / 256), 256, 0, c->stream>>>((int)c->n, x, 0, x);
+  k_trsv_dense_blk<T, UPPER><<<(unsigned)nb, 256, 0, c->stream>>>((int)c->n, Mv, rhs, x, c->flags + 3);
+  return true;
+}
+
 template <typename T, bool UPPER>
 static void launch_trsv(lsq_ctx *c, const T *rhs, T *x) {
+  if (launch_trsv_dense_blk<T, UPPER>(c, rhs, x)) return;
   const TriDev &d = UPPER ? c->tri_b : c->tri_f;
   if (c->trsv_chain) {
     switch (c->trsv_e) {

@@ -1495,16 +1495,24 @@ __global__ __launch_bounds__(256) void k_trsv_dense_blk(int n, const T *__restri
   if (q == 0 && r < jn) bsh[r] = rhs[j0 + r] - acc;
   __syncthreads();
   if (tid < kWave) {
+    // all 64 steps, unrolled, the block's matrix column for 8 steps read from
+    // LDS before them; rows past n hold zeros and change nothing
     T b = lane < jn ? bsh[lane] : (T)0;
     const T inv = lane < jn ? (T)1 / dblk[lane][lane] : (T)0;
     T xv = 0;
-    for (int s = 0; s < jn; ++s) {
-      const int i = UPPER ? jn - 1 - s : s;
-      const T xi = readlane_d(b * inv, i);
-      xv = lane == i ? xi : xv;
-      const bool dep = UPPER ? lane < i : (lane > i && lane < jn);
-      const T mri = dblk[lane][i];
-      b = dep ? b - mri * xi : b;
+#pragma unroll
+    for (int s0 = 0; s0 < kDB; s0 += 8) {
+      T mr[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) mr[k] = dblk[lane][UPPER ? kDB - 1 - (s0 + k) : s0 + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int i = UPPER ? kDB - 1 - (s0 + k) : s0 + k;
+        const T xi = readlane_d(b * inv, i);
+        xv = lane == i ? xi : xv;
+        const bool dep = UPPER ? lane < i : lane > i;
+        b = dep ? b - mr[k] * xi : b;
+      }
     }
     if (lane < jn) st_sync(x + j0 + lane, xv);
   }

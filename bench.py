@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--near-levels", type=int, default=0, help="triangular-solve near/far split (0: library default)")
     ap.add_argument("--chain-levels", type=int, default=0,
                     help="triangular-solve chain wave levels (0: library default, -1: chain mode off)")
+    ap.add_argument("--nrhs", type=int, default=0,
+                    help="also time one setup followed by this many right-hand sides (lsq_solve_many; float64)")
     ap.add_argument("--max-iter", type=int, default=0, help="PCG iteration cap (0: library default, 10 n)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device twice (HBM counter calibration) and exit")
@@ -243,6 +245,32 @@ def main():
                              "iters_mean": float(np.mean(its)), "iters_std": float(np.std(its)),
                              "iters_min": int(min(its)), "iters_max": int(max(its)),
                              "chain_levels_and_max": chains}
+
+    if args.nrhs > 0:
+        # one setup serving several right-hand sides: the setup's b and
+        # nrhs - 1 seeded Gaussian columns of the same norm
+        g = torch.Generator(device="cpu").manual_seed(1234)
+        cols = [b] + [torch.randn(p.m, generator=g, dtype=torch.float64).cuda() for _ in range(args.nrhs - 1)]
+        B = torch.stack([c * (b.norm() / c.norm()) for c in cols], dim=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kw = dict(C_=cfg["C"], sweeps=cfg["sweeps"], seed=0, mode="fp64", atap_algo=args.atap_algo,
+                  near_levels=args.near_levels, chain_levels=args.chain_levels, max_iter=args.max_iter)
+        if p.fmt == "dense":
+            s = Solver(dev["A"], b, **kw)
+        else:
+            s = Solver(values=dev["values"], row_ptr=dev["row_ptr"], col_idx=dev["col_idx"], shape=(p.m, p.n),
+                       b=b, **kw)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, infos_m = s.solve_many(B)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        s.close()
+        out["multi_rhs"] = {"nrhs": args.nrhs, "setup_ms": (t2 - t1) * 1e3, "solve_ms": (t3 - t2) * 1e3,
+                            "ms_per_rhs": (t3 - t1) * 1e3 / args.nrhs,
+                            "iters": [int(i["iters"]) for i in infos_m],
+                            "converged": all(int(i["converged"]) == 1 for i in infos_m)}
 
     if not args.no_cg_baseline:
         # the paper's comparison column: CG on the normalised normal equations

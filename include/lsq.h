@@ -172,6 +172,26 @@ int lsq_setup(const lsq_matrix *A, const double *b, double C, int32_t sweeps, ui
  * Returns LSQ_OK, LSQ_ENOCONV (x still written), LSQ_EBREAKDOWN, LSQ_EHIP. */
 int lsq_solve(lsq_ctx *ctx, double *x, lsq_info *info);
 
+/* Several right-hand sides on one setup (not in the paper): Algorithm 2
+ * steps 1-3 read A only, so the sample, M and the level sets of lsq_setup
+ * serve every b; step 4 (PCG) runs once per column, in column order, each
+ * exactly as lsq_solve with that column in place of the setup's b.
+ *   nrhs   number of columns (>= 0; 0 returns LSQ_OK and touches nothing)
+ *   B      device float64, column j at B + j*ldb (m entries), ldb >= m;
+ *          borrowed for the call only
+ *   X      device float64, column j at X + j*ldx (n entries), ldx >= n;
+ *          output, columns must not overlap B
+ *   infos  host lsq_info[nrhs], nullable: one record per column
+ * Every column of B is checked for NaN/Inf before any is solved
+ * (LSQ_ENONFINITE, nothing written). Returns LSQ_OK; LSQ_ENOCONV if some
+ * column missed the tolerance (all columns still solved and written); the
+ * first negative status (LSQ_EBREAKDOWN, LSQ_EHIP), after which later
+ * columns are not solved. The setup's own b is kept for later lsq_solve.
+ * Each column's work is that of one lsq_solve: the per-iteration kernels are
+ * not batched across columns. */
+int lsq_solve_many(lsq_ctx *ctx, int32_t nrhs, const double *B, int64_t ldb, double *X, int64_t ldx,
+                   lsq_info *infos);
+
 /* Differentiable form (not in the paper): given the solution x of lsq_solve
  * and grad_x = dL/dx, solves the adjoint A^T A lambda = grad_x with the same
  * preconditioner and mode, then forms

@@ -859,6 +859,43 @@ extern "C" int lsq_solve(lsq_ctx *ctx, double *x, lsq_info *info) {
   return rc;
 }
 
+// several right-hand sides on one setup: the sample, M and its level sets do
+// not depend on b (Algorithm 2 steps 1-3 read A only), so each column only
+// repeats step 4
+extern "C" int lsq_solve_many(lsq_ctx *ctx, int32_t nrhs, const double *B, int64_t ldb, double *X, int64_t ldx,
+                              lsq_info *infos) {
+  if (!ctx) return LSQ_EINVAL;
+  if (nrhs < 0 || (nrhs > 0 && (!B || !X || ldb < ctx->m || ldx < ctx->n))) RET(LSQ_EINVAL);
+  if (nrhs == 0) return LSQ_OK;
+  hipStream_t st = ctx->stream;
+  // every column is checked before any is solved
+  launch_fill_i32(ctx->flags, 1, 0, st);
+  for (int32_t j = 0; j < nrhs; ++j)
+    k_check_finite<<<grid_n(ctx->m), 256, 0, st>>>(ctx->m, B + (int64_t)j * ldb, ctx->flags);
+  int32_t f0 = 0;
+  LSQ_HIP_CHECK(hipMemcpyAsync(&f0, ctx->flags, sizeof(f0), hipMemcpyDeviceToHost, st));
+  LSQ_HIP_CHECK(hipStreamSynchronize(st));
+  if (f0 & 2) {
+    ctx->err = "B contains NaN or Inf";
+    RET(LSQ_ENONFINITE);
+  }
+  const double *b0 = ctx->b;
+  int worst = LSQ_OK;
+  for (int32_t j = 0; j < nrhs; ++j) {
+    ctx->b = B + (int64_t)j * ldb;
+    lsq_info inf;
+    const int rc = lsq_solve(ctx, X + (int64_t)j * ldx, &inf);
+    if (infos) infos[j] = inf;
+    if (rc < 0) {
+      worst = rc;
+      break;
+    }
+    if (rc != LSQ_OK) worst = rc;
+  }
+  ctx->b = b0;
+  return worst;
+}
+
 extern "C" int lsq_backward(lsq_ctx *ctx, const double *x, const double *grad_x, double *lambda, double *grad_b,
                             void *grad_A, lsq_info *info) {
   if (!ctx) return LSQ_EINVAL;

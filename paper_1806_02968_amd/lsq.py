@@ -21,8 +21,8 @@ LSQ_DENSE, LSQ_CSR = 0, 1
 LSQ_F64, LSQ_F32 = 0, 1
 LSQ_MODE_FP64, LSQ_MODE_FP32_REFINE = 0, 1
 
-EXPORTS = ("lsq_default_options", "lsq_setup", "lsq_solve", "lsq_backward", "lsq_get_setup", "lsq_get_M_nnz",
-           "lsq_get_M", "lsq_apply_P", "lsq_apply_K", "lsq_get_info", "lsq_get_kernel_stats", "lsq_destroy",
+EXPORTS = ("lsq_default_options", "lsq_setup", "lsq_solve", "lsq_solve_many", "lsq_backward", "lsq_get_setup",
+           "lsq_get_M_nnz", "lsq_get_M", "lsq_apply_P", "lsq_apply_K", "lsq_get_info", "lsq_get_kernel_stats", "lsq_destroy",
            "lsq_strerror", "lsq_last_error")
 
 
@@ -86,6 +86,8 @@ def lib():
         L.lsq_setup.restype = C.c_int
         L.lsq_solve.argtypes = [P, P, C.POINTER(Info)]
         L.lsq_solve.restype = C.c_int
+        L.lsq_solve_many.argtypes = [P, C.c_int32, P, I64, P, I64, P]
+        L.lsq_solve_many.restype = C.c_int
         L.lsq_backward.argtypes = [P, P, P, P, P, P, C.POINTER(Info)]
         L.lsq_backward.restype = C.c_int
         L.lsq_get_setup.argtypes = [P, P, P, P, P]
@@ -235,6 +237,20 @@ class Solver:
         rc = lib().lsq_solve(self._ctx, _ptr(x), C.byref(info))
         self._check(rc, "lsq_solve")
         return x, info.as_dict()
+
+    def solve_many(self, B):
+        """Columns of B (m x k, float64 on the device) solved on this setup;
+        returns X (n x k) and one info dict per column."""
+        import torch
+        if B.dim() != 2 or B.shape[0] != self.m or B.dtype != torch.float64 or not B.is_cuda:
+            raise ValueError("B must be a float64 device tensor of shape (%d, k)" % self.m)
+        k = int(B.shape[1])
+        Bc = B.t().contiguous()  # column j at Bc[j], stride m
+        X = torch.empty(k, self.n, dtype=torch.float64, device="cuda")  # row j = column j of the result
+        infos = (Info * max(k, 1))()
+        rc = lib().lsq_solve_many(self._ctx, k, _ptr(Bc), self.m, _ptr(X), self.n, infos)
+        self._check(rc, "lsq_solve_many")
+        return X.t(), [infos[j].as_dict() for j in range(k)]
 
     def backward(self, x, grad_x, want_grad_A: bool = True, want_grad_b: bool = True):
         import torch

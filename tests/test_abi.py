@@ -86,6 +86,7 @@ def test_setup_rejects_bad_arguments_on_the_host(L):
 
 def test_null_context_calls(L):
     assert L.lsq_solve(None, None, None) == -1
+    assert L.lsq_solve_many(None, 1, None, 0, None, 0, None) == -1
     assert L.lsq_backward(None, None, None, None, None, None, None) == -1
     assert L.lsq_get_M_nnz(None) == -1
     L.lsq_destroy(None)
